@@ -1,0 +1,156 @@
+/*
+ * mc.h -- C ABI of the MI355X (gfx950) implementation of the parallel
+ * multicanonical Markov-chain method of Sugihara, Higo and Nakamura,
+ * "Parallelization of Markov Chain Generation and its Application to the
+ * Multicanonical Method" (arXiv 0812.2964), applied to the periodic 2D Ising
+ * model of its Sec. 4.
+ *
+ * One iteration of the method, for one lattice size:
+ *
+ *     mc_run_chains     Algorithm step 2: every chain makes n_sweeps sweeps
+ *     mc_join           Algorithm steps 3-5: detailed-balance joints
+ *     mc_update_weights eq. (new_weight) in logarithms (Sec. 3.1, Sec. 4.2)
+ *
+ * Conventions (the readings of the paper this library implements):
+ *   - N = L*L spins, J = 1, H = -sum_<ij> s_i s_j with periodic boundaries.
+ *   - A "configuration" of a chain is its lattice after one sweep: N
+ *     single-spin Metropolis attempts in typewriter order (site j = y*L + x).
+ *   - Level m = (E + 2N)/4 in [0, N]; bin b = m >> bin_shift; n_bins =
+ *     (N >> bin_shift) + 1.  ln w is stored per bin in binary64.
+ *   - Acceptance of a move that changes ln w by d: u <= tau(d), where u is a
+ *     32-bit Philox4x32-10 word and tau(d) = 2^32-1 for d >= 0, else
+ *     min(floor(exp(d) 2^32), 2^32-1), with exp and log evaluated by a fixed
+ *     Cody-Waite/Taylor sequence of IEEE-754 operations (bit-reproducible).
+ *   - Random words: counter (j>>2, a, chain, domain), key (seed, L), word j&3;
+ *     domain 0 = sweeps (a = global sweep index), 1 = initial spins, 2 = joint
+ *     tests (a = round, j = 0-based position in the chain).
+ *   - Energies in traces are E/4 (= m - N/2): int16 elements for L <= 254,
+ *     int32 for L = 256.  Traces are row-major [n_chains][n_sweeps].
+ *
+ * Memory and streams: a context owns the chain state (bit-packed lattices,
+ * levels, counters, seam), the ln w tables and the acceptance thresholds, in
+ * device memory it allocates at creation.  Traces, histograms and cut arrays
+ * are device buffers owned by the caller.  Every call enqueues work on the
+ * HIP stream given at creation and returns without waiting, except those
+ * that write host memory, which synchronise that stream.
+ *
+ * Errors: every call returns an mc_status.  Argument errors are detected
+ * before anything is enqueued and leave the context unchanged.  A failed HIP
+ * call marks the context broken (MC_EHIP), after which every call except
+ * mc_destroy fails.  mc_last_error() returns a message for the last error on
+ * the calling thread.  Calls on one context are not thread-safe.
+ */
+#ifndef MC_H
+#define MC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mc_ctx mc_ctx;
+
+typedef enum {
+    MC_OK = 0,
+    MC_EINVAL = -1,     /* bad argument                                       */
+    MC_ENOMEM = -2,     /* device allocation failed                           */
+    MC_ENODEV = -3,     /* no usable GPU                                      */
+    MC_EHIP = -4,       /* a HIP runtime call failed; the context is broken   */
+    MC_ESTATE = -5,     /* call out of order (e.g. join of sweeps not run)    */
+    MC_EOVERFLOW = -6,  /* histogram or counter range would be exceeded       */
+    MC_ECORRUPT = -7    /* a state blob failed its checks                     */
+} mc_status;
+
+/* One lattice size of a context.  Sizes are independent ensembles: each has
+   its own chains, ln w table, seam and counters. */
+typedef struct {
+    int32_t L;         /* even, 4 <= L <= 256                                  */
+    int32_t n_chains;  /* p of the paper, >= 1, <= 2^20                        */
+    uint32_t seed;     /* Philox key word 0 (word 1 is L)                      */
+    int32_t bin_shift; /* 0: one bin per level; 1: two levels (8 energy units) */
+} mc_size;
+
+/* Create a context on the current HIP device for n_sizes (1..16) lattice
+   sizes, bound to hip_stream (a hipStream_t; NULL = the null stream).
+   Algorithm step 1: every chain c of every size gets its initial spins
+   (s_j = +1 iff bit 31 of the domain-1 word of site j is set), its level is
+   computed, ln w is set to 0 (w^(1) = 1, Sec. 3.1), the seam is "none" and the
+   sweep and round counters are 0.  On success *out receives the context.
+   Errors: MC_EINVAL (sizes), MC_ENODEV (no GPU), MC_ENOMEM, MC_EHIP. */
+mc_status mc_create(const mc_size *sizes, int32_t n_sizes, void *hip_stream, mc_ctx **out);
+
+/* Release everything the context owns (waits for its stream first). NULL is a no-op. */
+mc_status mc_destroy(mc_ctx *ctx);
+
+/* Number of bins / trace element size in bytes / lattice words per chain of a size. */
+int32_t mc_n_bins(const mc_ctx *ctx, int32_t size_idx);
+int32_t mc_trace_elem_bytes(const mc_ctx *ctx, int32_t size_idx);
+int32_t mc_lattice_words(const mc_ctx *ctx, int32_t size_idx);
+
+/* Set ln w of one size from host memory (copied; n_bins values, all finite),
+   or to 0 everywhere when lnW_host is NULL, and tabulate the acceptance
+   thresholds.  Sec. 3.1 (initial weight w^(1) = 1) and Sec. 4.2 (weights kept
+   as logarithms).  Errors: MC_EINVAL (n_bins mismatch, non-finite value). */
+mc_status mc_init_weights(mc_ctx *ctx, int32_t size_idx, const double *lnW_host, int32_t n_bins);
+
+/* Algorithm step 2 for every size of the context, in one launch: each chain
+   makes n_sweeps sweeps from where it stopped (chains are independent from
+   first to last, Sec. 2 remarks).  For size s:
+     trace_dev[s]: device, [n_chains][n_sweeps] of E/4 after each sweep;
+     hist_dev[s]:  device int32 [n_bins]; the bin of every configuration of
+                   every chain is added to it (so it must hold zeros, or the
+                   joint histogram so far, on entry).
+   trace_dev and hist_dev are host arrays of n_sizes device pointers.
+   Errors: MC_EINVAL (n_sweeps < 1, NULL pointer), MC_EOVERFLOW (more than
+   2^31-1 configurations would be counted before the next weight update). */
+mc_status mc_run_chains(mc_ctx *ctx, int64_t n_sweeps, void *const *trace_dev, int32_t *const *hist_dev);
+
+/* Algorithm steps 3-5 for one size over the trace of the last mc_run_chains
+   (n_sweeps must match it).  For chain i = 0 .. n_chains-1 in order, the
+   configurations are tested against the seam (the energy of the last kept
+   configuration before chain i) with the Metropolis rule until one is
+   accepted; it and its successors are kept, the others discarded.  If none is
+   accepted the seam is carried on unchanged.  The first chain of the very
+   first round has no seam and is kept whole.
+     cut_dev:  device int32 [n_chains]: 1-based first kept position, or -1;
+     hist_dev: device int32 [n_bins]: the histogram mc_run_chains filled; the
+               discarded configurations are removed from it, so on return it
+               is the total histogram h(E) of the joined chain;
+     mode:     0 = detailed balance (the paper's method), 1 = keep every
+               chain whole (the naive splice compared in Sec. 5).
+   Errors: MC_EINVAL, MC_ESTATE (no matching mc_run_chains). */
+mc_status mc_join(mc_ctx *ctx, int32_t size_idx, const void *trace_dev, int64_t n_sweeps, int32_t *cut_dev,
+                  int32_t *hist_dev, int32_t mode);
+
+/* Eq. (new_weight) in logarithms for one size: ln w(b) -= ln h(b) for every
+   bin with h(b) > 0, the flatness test (over bins holding a reachable level:
+   5 n min h >= 4 sum h, in integers), re-tabulation of the thresholds, and
+   hist_dev set to zero.  Optional host outputs (each may be NULL; if any is
+   non-NULL the call synchronises): lnW_out_host [n_bins], is_flat, retained
+   (configurations kept by the joints since the previous update).
+   Errors: MC_EINVAL. */
+mc_status mc_update_weights(mc_ctx *ctx, int32_t size_idx, int32_t *hist_dev, double *lnW_out_host,
+                            int32_t *is_flat, int64_t *retained);
+
+/* Inspection (synchronising, host outputs):
+   levels_host [n_chains] current level m of each chain;
+   words_host  [mc_lattice_words] the bit-packed lattice of one chain: row y,
+               word w at [y*W + w], bit x%32 of word x/32 is site (x, y), 1 = +1;
+   seam / counters: seam level (-1 = none), round index, global sweep index. */
+mc_status mc_get_levels(mc_ctx *ctx, int32_t size_idx, int32_t *levels_host);
+mc_status mc_get_lattice(mc_ctx *ctx, int32_t size_idx, int32_t chain, uint32_t *words_host, int32_t n_words);
+mc_status mc_get_counters(mc_ctx *ctx, int32_t size_idx, int32_t *seam, uint32_t *round, uint32_t *sweep);
+
+/* Wait for all work of the context. */
+mc_status mc_sync(mc_ctx *ctx);
+
+/* Message of the last error on this thread ("" if none). */
+const char *mc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MC_H */

@@ -1,0 +1,228 @@
+"""Python binding of libmcgpu.so, the MI355X (gfx950) implementation of the
+parallel multicanonical Markov-chain method of arXiv 0812.2964 (Sugihara,
+Higo, Nakamura) on the periodic 2D Ising model.
+
+This module only marshals arguments: every step of the method runs in the
+library's HIP kernels.  PyTorch provides device memory (traces, histograms,
+cut arrays are torch tensors) and the HIP stream.  There is no CPU fallback:
+if the library is missing or no GPU is present, the calls raise.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmcgpu.so")
+
+MC_OK, MC_EINVAL, MC_ENOMEM, MC_ENODEV, MC_EHIP, MC_ESTATE, MC_EOVERFLOW, MC_ECORRUPT = 0, -1, -2, -3, -4, -5, -6, -7
+_STATUS = {0: "MC_OK", -1: "MC_EINVAL", -2: "MC_ENOMEM", -3: "MC_ENODEV", -4: "MC_EHIP", -5: "MC_ESTATE",
+           -6: "MC_EOVERFLOW", -7: "MC_ECORRUPT"}
+
+# Symbols declared in include/mc.h (checked by the CPU test-suite).
+EXPORTED = ["mc_create", "mc_destroy", "mc_n_bins", "mc_trace_elem_bytes", "mc_lattice_words", "mc_init_weights",
+            "mc_run_chains", "mc_join", "mc_update_weights", "mc_get_levels", "mc_get_lattice", "mc_get_counters",
+            "mc_sync", "mc_last_error"]
+
+
+class MCError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (_STATUS.get(status, status), msg))
+        self.status = status
+
+
+class _Size(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("n_chains", ctypes.c_int32), ("seed", ctypes.c_uint32),
+                ("bin_shift", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library (after torch, so one HIP runtime serves both)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libmcgpu.so is not built: run __graft_entry__.build() or "
+                           "python paper_0812_2964_amd/build.py")
+    import torch  # noqa: F401  (loads the HIP runtime the library links against)
+
+    L = ctypes.CDLL(LIB_PATH)
+    p, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    L.mc_create.argtypes = [ctypes.POINTER(_Size), i32, p, ctypes.POINTER(p)]
+    L.mc_destroy.argtypes = [p]
+    for f in ("mc_n_bins", "mc_trace_elem_bytes", "mc_lattice_words"):
+        getattr(L, f).argtypes = [p, i32]
+        getattr(L, f).restype = i32
+    L.mc_init_weights.argtypes = [p, i32, p, i32]
+    L.mc_run_chains.argtypes = [p, i64, p, p]
+    L.mc_join.argtypes = [p, i32, p, i64, p, p, i32]
+    L.mc_update_weights.argtypes = [p, i32, p, p, p, p]
+    L.mc_get_levels.argtypes = [p, i32, p]
+    L.mc_get_lattice.argtypes = [p, i32, i32, p, i32]
+    L.mc_get_counters.argtypes = [p, i32, p, p, p]
+    L.mc_sync.argtypes = [p]
+    L.mc_last_error.restype = ctypes.c_char_p
+    for f in EXPORTED:
+        if f not in ("mc_n_bins", "mc_trace_elem_bytes", "mc_lattice_words", "mc_last_error"):
+            getattr(L, f).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(st):
+    if st != MC_OK:
+        raise MCError(st, lib().mc_last_error().decode())
+
+
+def _dev_ptr(t, dtype, numel=None, name="tensor"):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if numel is not None and t.numel() != numel:
+        raise ValueError("%s must have %d elements, has %d" % (name, numel, t.numel()))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """Chains of one or more lattice sizes on the current GPU (mc_create).
+
+    sizes: list of (L, n_chains, seed, bin_shift) tuples.
+    """
+
+    def __init__(self, sizes, stream=None):
+        import torch
+
+        self.sizes = [tuple(s) for s in sizes]
+        arr = (_Size * len(sizes))(*[_Size(int(L), int(p), int(seed), int(bs)) for (L, p, seed, bs) in sizes])
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        _check(lib().mc_create(arr, len(sizes), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- geometry ---------------------------------------------------------
+    def n_bins(self, i=0):
+        return lib().mc_n_bins(self._h, i)
+
+    def trace_dtype(self, i=0):
+        import torch
+
+        return torch.int16 if lib().mc_trace_elem_bytes(self._h, i) == 2 else torch.int32
+
+    def lattice_words(self, i=0):
+        return lib().mc_lattice_words(self._h, i)
+
+    def new_trace(self, n_sweeps, i=0):
+        import torch
+
+        return torch.empty((self.sizes[i][1], n_sweeps), dtype=self.trace_dtype(i), device="cuda")
+
+    def new_hist(self, i=0):
+        import torch
+
+        return torch.zeros(self.n_bins(i), dtype=torch.int32, device="cuda")
+
+    def new_cut(self, i=0):
+        import torch
+
+        return torch.empty(self.sizes[i][1], dtype=torch.int32, device="cuda")
+
+    # -- the method -------------------------------------------------------
+    def init_weights(self, lnW=None, i=0):
+        nb = self.n_bins(i)
+        if lnW is None:
+            _check(lib().mc_init_weights(self._h, i, None, nb))
+            return
+        w = np.ascontiguousarray(np.asarray(lnW, dtype=np.float64))
+        if w.size != nb:
+            raise ValueError("lnW must have %d bins" % nb)
+        _check(lib().mc_init_weights(self._h, i, w.ctypes.data_as(ctypes.c_void_p), nb))
+
+    def run_chains(self, n_sweeps, traces, hists):
+        """traces/hists: one tensor per size (or a single tensor for one size)."""
+        import torch
+
+        if isinstance(traces, torch.Tensor):
+            traces = [traces]
+        if isinstance(hists, torch.Tensor):
+            hists = [hists]
+        if len(traces) != len(self.sizes) or len(hists) != len(self.sizes):
+            raise ValueError("need one trace and one hist per size")
+        tp = (ctypes.c_void_p * len(self.sizes))()
+        hp = (ctypes.c_void_p * len(self.sizes))()
+        for i in range(len(self.sizes)):
+            tp[i] = _dev_ptr(traces[i], self.trace_dtype(i), self.sizes[i][1] * n_sweeps, "trace").value
+            hp[i] = _dev_ptr(hists[i], torch.int32, self.n_bins(i), "hist").value
+        _check(lib().mc_run_chains(self._h, int(n_sweeps), tp, hp))
+
+    def join(self, trace, cut, hist, mode=0, i=0):
+        import torch
+
+        M = trace.shape[-1]
+        _check(lib().mc_join(self._h, i, _dev_ptr(trace, self.trace_dtype(i), self.sizes[i][1] * M, "trace"), int(M),
+                             _dev_ptr(cut, torch.int32, self.sizes[i][1], "cut"),
+                             _dev_ptr(hist, torch.int32, self.n_bins(i), "hist"), int(mode)))
+
+    def update_weights(self, hist, i=0, want=True):
+        """Returns (lnW numpy array, flat flag, retained count) when want."""
+        import torch
+
+        hp = _dev_ptr(hist, torch.int32, self.n_bins(i), "hist")
+        if not want:
+            _check(lib().mc_update_weights(self._h, i, hp, None, None, None))
+            return None
+        w = np.zeros(self.n_bins(i), dtype=np.float64)
+        flat = ctypes.c_int32()
+        ret = ctypes.c_int64()
+        _check(lib().mc_update_weights(self._h, i, hp, w.ctypes.data_as(ctypes.c_void_p), ctypes.byref(flat),
+                                       ctypes.byref(ret)))
+        return w, bool(flat.value), int(ret.value)
+
+    # -- inspection -------------------------------------------------------
+    def levels(self, i=0):
+        out = np.zeros(self.sizes[i][1], dtype=np.int32)
+        _check(lib().mc_get_levels(self._h, i, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def lattice(self, chain, i=0):
+        n = self.lattice_words(i)
+        out = np.zeros(n, dtype=np.uint32)
+        _check(lib().mc_get_lattice(self._h, i, chain, out.ctypes.data_as(ctypes.c_void_p), n))
+        return out
+
+    def spins(self, chain, i=0):
+        """Lattice of one chain as +-1 int8 in site order j = y*L + x."""
+        L = self.sizes[i][0]
+        W = (L + 31) // 32
+        words = self.lattice(chain, i).reshape(L, W)
+        x = np.arange(L)
+        bits = (words[:, x // 32] >> (x % 32).astype(np.uint32)) & 1
+        return (bits.astype(np.int8) * 2 - 1).reshape(-1)
+
+    def counters(self, i=0):
+        seam = ctypes.c_int32()
+        rnd = ctypes.c_uint32()
+        sw = ctypes.c_uint32()
+        _check(lib().mc_get_counters(self._h, i, ctypes.byref(seam), ctypes.byref(rnd), ctypes.byref(sw)))
+        return seam.value, rnd.value, sw.value
+
+    def sync(self):
+        _check(lib().mc_sync(self._h))

@@ -1,0 +1,46 @@
+// mc_internal.h -- device-side state layout and kernel launchers of the library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mcgpu {
+
+// Per-size control block in device memory.  Counters advance on the device,
+// so a captured sequence of launches stays correct when replayed.
+struct Ctl {
+    uint32_t g;             // global index of the next sweep (random-word domain 0)
+    uint32_t r;             // index of the next joint round (domain 2)
+    int32_t sigma;          // seam level, -1 = none yet
+    int32_t flat;           // flatness of the last update
+    int64_t retained;       // configurations kept by joints since the last update
+    int64_t retained_last;  // the same, frozen by the last update
+    int32_t iter;           // updates done so far
+    int32_t flat_iter;      // first update (1-based) that was flat, 0 = none
+};
+
+// Device view of one lattice size.
+struct SizeDev {
+    int32_t L, N, W;        // W = 32-bit words per lattice row
+    int32_t P;              // chains
+    int32_t bin_shift, n_bins;
+    uint32_t seed;
+    int32_t trace_bytes;    // 2 (int16) or 4 (int32)
+    uint32_t *lat;          // [L*W][P] chain-interleaved bit-packed rows
+    int32_t *lev;           // [P] current level of each chain
+    double *lnW;            // [n_bins]
+    uint32_t *tab;          // [(N+1)*8] thresholds, entry (m, a) at m*8 + a, a = dm + 2
+    Ctl *ctl;
+    int32_t *scratch_cut;   // [P] speculative cut points of the joint
+};
+
+// Kernel launchers (mc_kernels.hip).  All enqueue on `st` and return the
+// launch status.
+hipError_t launch_init(const SizeDev &s, hipStream_t st);
+hipError_t launch_tabulate(const SizeDev &s, hipStream_t st);
+hipError_t launch_sweeps(const SizeDev *sizes, int n_sizes, int64_t M, void *const *trace, int32_t *const *hist,
+                         int chains_per_block, hipStream_t st);
+hipError_t launch_join(const SizeDev &s, const void *trace, int64_t M, int32_t *cut, int32_t *hist, int mode,
+                       hipStream_t st);
+hipError_t launch_update(const SizeDev &s, int32_t *hist, hipStream_t st);
+
+}  // namespace mcgpu

@@ -1,0 +1,260 @@
+"""GPU path (through the C ABI) against the CPU oracle, element by element.
+
+Integer outputs (energy traces, histograms, cut points, seams, lattices,
+levels) must be identical; ln w after an update must be identical bit for bit
+(both sides evaluate ln with the same fixed sequence of binary64 operations).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _mc():
+    import paper_0812_2964_amd as mc
+
+    return mc
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def gpu_round(ctx, M, i=0, mode=0, update=True, hist=None):
+    """One round of a one-size context: run, join, and (optionally) update.
+    hist carries the joint histogram across rounds that are not followed by
+    an update (Algorithm step 6)."""
+    tr = ctx.new_trace(M, i)
+    h = hist if hist is not None else ctx.new_hist(i)
+    cut = ctx.new_cut(i)
+    ctx.run_chains(M, tr, h)
+    raw = _np(h).copy()
+    ctx.join(tr, cut, h, mode, i)
+    joined = _np(h).copy()
+    out = dict(trace=_np(tr).astype(np.int32), raw=raw, cut=_np(cut), joined=joined)
+    if update:
+        w, flat, ret = ctx.update_weights(h, i)
+        out.update(lnW=w, flat=flat, retained=ret, hist_after=_np(h).copy())
+    return out
+
+
+def oracle_round(R, M, mode=0, update=True):
+    H0 = R.H.copy()
+    tr, raw = R.run(M)
+    cut, H = R.join(tr, mode)
+    out = dict(trace=tr, raw=raw + H0, cut=cut, joined=R.H.copy(), retained=R.retained)
+    if update:
+        out["flat"] = R.update()
+        out["lnW"] = R.lnW.copy()
+    return out
+
+
+def assert_round_equal(g, o, update=True):
+    assert np.array_equal(g["trace"], o["trace"]), "trace differs"
+    assert np.array_equal(g["raw"], o["raw"]), "raw histogram differs"
+    assert np.array_equal(g["cut"], o["cut"]), "cut points differ"
+    assert np.array_equal(g["joined"], o["joined"]), "joined histogram differs"
+    if update:
+        assert g["retained"] == o["retained"]
+        assert g["flat"] == o["flat"]
+        assert np.array_equal(g["lnW"].view(np.uint64), o["lnW"].view(np.uint64)), "ln w differs"
+        assert not g["hist_after"].any()
+
+
+def assert_state_equal(ctx, R, i=0):
+    assert np.array_equal(ctx.levels(i), R.m)
+    for c in sorted({0, R.p // 2, R.p - 1}):
+        assert np.array_equal(ctx.spins(c, i), R.spins[c])
+    seam, rnd, sweep = ctx.counters(i)
+    assert (seam, rnd, sweep) == (R.sigma, R.r, R.g)
+
+
+def test_initial_state_matches_oracle():
+    mc = _mc()
+    for L, P in [(8, 16), (32, 70), (6, 5), (128, 3)]:
+        ctx = mc.Context([(L, P, 1, 1)])
+        R = O.Run(L, P, seed=1, bin_shift=1)
+        assert np.array_equal(ctx.levels(), R.m)
+        for c in range(P):
+            assert np.array_equal(ctx.spins(c), R.spins[c])
+        ctx.close()
+
+
+def test_config_L8_16chains_full_recursion_bitexact():
+    """L = 8, 16 chains, 10^4 sweeps per iteration, 10 iterations of the
+    recursion from ln w = 0, width-8 bins (33 bins), seed 1."""
+    mc = _mc()
+    ctx = mc.Context([(8, 16, 1, 1)])
+    R = O.Run(8, 16, seed=1, bin_shift=1)
+    ctx.init_weights(None)
+    flats = []
+    for it in range(10):
+        g = gpu_round(ctx, 10000)
+        o = oracle_round(R, 10000)
+        assert_round_equal(g, o)
+        flats.append(g["flat"])
+    assert_state_equal(ctx, R)
+    assert any(flats)  # this workload reaches a flat histogram within 10 iterations
+    ctx.close()
+
+
+def _prior_lnW():
+    return np.load(os.path.join(HERE, "golden", "lnW_L32_prior.npy"))
+
+
+def test_L32_prior_weight_rounds_bitexact():
+    mc = _mc()
+    P = 130  # two full blocks of 64 and a ragged tail
+    ctx = mc.Context([(32, P, 1, 1)])
+    w = _prior_lnW()
+    ctx.init_weights(w)
+    R = O.Run(32, P, seed=1, bin_shift=1, lnW=w)
+    h = ctx.new_hist()
+    for M, upd in [(150, False), (97, True), (64, True)]:
+        g = gpu_round(ctx, M, update=upd, hist=h)
+        o = oracle_round(R, M, update=upd)
+        assert_round_equal(g, o, update=upd)
+    assert_state_equal(ctx, R)
+    ctx.close()
+
+
+@pytest.mark.parametrize("L,P,bs,M", [(4, 65, 0, 40), (6, 9, 1, 30), (10, 9, 0, 20), (12, 64, 1, 30),
+                                      (16, 70, 1, 25), (24, 33, 1, 12), (48, 20, 1, 6), (64, 40, 1, 5),
+                                      (64, 7, 0, 4), (128, 5, 1, 2), (256, 2, 1, 1)])
+def test_sizes_and_binnings_bitexact(L, P, bs, M):
+    mc = _mc()
+    N = L * L
+    nb = (N >> bs) + 1
+    rng = np.random.default_rng(L * 7 + bs)
+    # a smooth, non-trivial weight: favours the middle of the energy range and
+    # rejects a good share of moves
+    x = (np.arange(nb) - nb / 2) / nb
+    w = -0.25 * N * x * x + rng.normal(0, 0.3, nb)
+    ctx = mc.Context([(L, P, 5, bs)])
+    ctx.init_weights(w)
+    R = O.Run(L, P, seed=5, bin_shift=bs, lnW=w)
+    for _ in range(2):
+        g = gpu_round(ctx, M)
+        o = oracle_round(R, M)
+        assert_round_equal(g, o)
+    assert_state_equal(ctx, R)
+    ctx.close()
+
+
+def test_join_hand_built_traces_and_modes():
+    import torch
+
+    mc = _mc()
+    L, N, bs = 4, 16, 0
+    lnW = np.zeros(N + 1)
+    lnW[10:] = -200.0
+    lv = np.array([[3, 4, 12, 5, 6, 7], [11, 12, 4, 12, 5, 8], [14, 13, 12, 11, 10, 15], [12, 2, 3, 3, 3, 9]])
+    P, M = lv.shape
+    for mode in (0, 1):
+        ctx = mc.Context([(L, P, 1, bs)])
+        ctx.init_weights(lnW)
+        tr_dev = ctx.new_trace(M)
+        h = ctx.new_hist()
+        ctx.run_chains(M, tr_dev, h)  # fills a real trace; replaced by the hand-built one below
+        hand = torch.tensor(lv - N // 2, dtype=ctx.trace_dtype()).cuda()
+        h.zero_()
+        cut = ctx.new_cut()
+        ctx.join(hand, cut, h, mode)
+        ocut, oH, oret, osig = O.join(L, bs, 1, lv - N // 2, lnW, -1, 0, mode)
+        assert np.array_equal(_np(cut), ocut)
+        # the joint removed exactly the discarded configurations
+        assert np.array_equal(-_np(h), np.bincount(lv.ravel(), minlength=N + 1) - oH)
+        seam, rnd, _ = ctx.counters()
+        assert seam == osig and rnd == 1
+        ctx.close()
+    assert list(ocut) == [1, 1, 1, 1]
+
+
+def test_call_order_and_overflow_errors():
+    mc = _mc()
+    ctx = mc.Context([(8, 4, 1, 1)])
+    tr = ctx.new_trace(10)
+    h = ctx.new_hist()
+    cut = ctx.new_cut()
+    with pytest.raises(mc.MCError) as e:
+        ctx.join(tr, cut, h)
+    assert e.value.status == mc.MC_ESTATE
+    ctx.run_chains(10, tr, h)
+    with pytest.raises(mc.MCError) as e:
+        ctx.join(ctx.new_trace(11), cut, h)
+    assert e.value.status == mc.MC_EINVAL
+    ctx.join(tr, cut, h)
+    with pytest.raises(mc.MCError):
+        ctx.init_weights(np.full(ctx.n_bins(), np.nan))
+    # 2^20 chains x 4096 sweeps would overflow the int32 histogram: refused
+    # before anything is launched
+    import ctypes
+
+    big = mc.Context([(8, 1 << 20, 1, 1)])
+    tp = (ctypes.c_void_p * 1)(tr.data_ptr())
+    hp = (ctypes.c_void_p * 1)(h.data_ptr())
+    assert mc.lib().mc_run_chains(big._h, 4096, tp, hp) == mc.MC_EOVERFLOW
+    ctx.close()
+    big.close()
+
+
+def test_bench_workload_full_size_sampled():
+    """The benchmark's workload at full size (L = 32, 4096 chains, 10^5 sweeps,
+    prior ln w) in the benchmark's launch configuration.  Sampled chains are
+    replayed by the oracle bit for bit; the histograms and every cut point
+    are checked through properties that hold at any size."""
+    mc = _mc()
+    L, P, M, N = 32, 4096, 100000, 1024
+    w = _prior_lnW()
+    ctx = mc.Context([(L, P, 1, 1)])
+    ctx.init_weights(w)
+    tr, h, cut = ctx.new_trace(M), ctx.new_hist(), ctx.new_cut()
+    ctx.run_chains(M, tr, h)
+    raw = _np(h).copy()
+    ctx.join(tr, cut, h)
+    joined = _np(h).copy()
+    seam, rnd, sweep = ctx.counters()
+    levels = ctx.levels()
+    spins = {c: ctx.spins(c) for c in (0, 2047, 4095)}
+    trace = _np(tr)
+    cuts = _np(cut)
+    ctx.close()
+    # sampled chains: the oracle replays them from their initial state
+    T = O.tabulate(L, 1, w).ravel()
+    for c in (0, 2047, 4095):
+        s0 = O.init_chain(L, 1, c)
+        m0 = (O.energy(L, s0) + 2 * N) // 4
+        s, m, otr, _ = O.sweeps(L, 1, 1, c, s0, m0, 0, M, w)
+        assert np.array_equal(trace[c].astype(np.int32), otr), c
+        assert np.array_equal(spins[c], s) and levels[c] == m
+    assert sweep == M and rnd == 1
+    # histograms: raw = every configuration; joined = the kept suffixes
+    lv = trace.astype(np.int64) + N // 2
+    assert raw.sum() == P * M
+    assert np.array_equal(raw, np.bincount((lv >> 1).ravel(), minlength=513))
+    keep = np.arange(M)[None, :] >= np.where(cuts > 0, cuts - 1, M)[:, None]
+    assert np.array_equal(joined, np.bincount((lv[keep] >> 1), minlength=513))
+    # every cut obeys the Metropolis test against its true seam
+    assert cuts[0] == 1  # the first chain of the first round has no seam
+    sigma = -1
+    checked = 0
+    for i in range(P):
+        c = cuts[i]
+        if sigma >= 0 and (i < 40 or i % 97 == 0):
+            ws = w[sigma >> 1]
+            upto = (c - 1) if c > 0 else M
+            for k in range(upto + (1 if c > 0 else 0)):
+                t = O.threshold(w[lv[i, k] >> 1] - ws)
+                acc = O.uniform(1, L, 2, 0, i, k) <= t
+                assert acc == (c > 0 and k == c - 1), (i, k, c)
+            checked += 1
+        if c > 0:
+            sigma = int(lv[i, M - 1])
+    assert seam == sigma
+    assert checked > 40
