@@ -101,43 +101,80 @@ __device__ __forceinline__ uint32_t bit_at(const Row<L> &r, int x) {
     return (r.w[x >> 5] >> (x & 31)) & 1u;
 }
 
-// One Metropolis attempt at site x of the current row (Sec. 4.1 energy,
-// Sec. 4.2 Metropolis rule).  cur holds the row as it is now (sites < x
-// already visited in this sweep); xu/xd are cur ^ up and cur ^ down taken at
-// the start of the row, exact for bit x because bit x of cur is untouched
-// until site x is visited.
+// Row r' with r'_x = r_{(x+1) mod L} (bit x of the result is the right-hand
+// neighbour of site x).  Padding bits above L stay zero.
 template <int L>
-__device__ __forceinline__ void attempt(int x, uint32_t u, Row<L> &cur, const Row<L> &xu, const Row<L> &xd, int &m,
-                                        const uint32_t *tab) {
-    const int xl = (x == 0) ? L - 1 : x - 1;
-    const int xr = (x == L - 1) ? 0 : x + 1;
-    const uint32_t sv = bit_at<L>(cur, x);
-    const uint32_t anti = bit_at<L>(xu, x) + bit_at<L>(xd, x) + (sv ^ bit_at<L>(cur, xl)) + (sv ^ bit_at<L>(cur, xr));
-    const uint32_t a = 4u - anti;  // flip moves the level by a - 2
-    const uint32_t t = tab[((uint32_t)m << 3) | a];
-    if (u <= t) {
-        cur.w[x >> 5] ^= 1u << (x & 31);
-        m += (int)a - 2;
+__device__ __forceinline__ Row<L> ring_next(const Row<L> &c) {
+    constexpr int W = (L + 31) / 32;
+    Row<L> r;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        r.w[w] = c.w[w] >> 1;
+        if (w + 1 < W) r.w[w] |= c.w[w + 1] << 31;
     }
+    r.w[W - 1] |= (c.w[0] & 1u) << ((L - 1) & 31);
+    return r;
 }
 
+// One row of typewriter Metropolis attempts (Sec. 2 step 2 with the energy of
+// Sec. 4.1 and the Metropolis rule of Sec. 4.2).
+//
+// Level bookkeeping: mi = 8 m + 4, so the threshold of a flip with `anti`
+// anti-aligned neighbours (level change a - 2 = 2 - anti) sits at tab[mi - anti]
+// and an accepted flip moves mi by D = 16 - 8 anti.
+//
+// The number of anti-aligned neighbours of site x is fixed at the start of the
+// row except for its left neighbour x-1, which may have flipped just before
+// (and, for x = L-1, its right neighbour 0).  So while the test at site x is
+// being decided, both thresholds site x+1 can need -- site x rejected (level
+// unchanged, left bond as at row start) or accepted (level moved by D, left
+// bond toggled) -- are already being read from LDS; the decision then only
+// selects one.  xu, xd, hb: bits x of (row ^ up), (row ^ down), (row ^ right
+// neighbour), all at row start.
 template <int L>
 __device__ __forceinline__ void sweep_row(uint32_t y, uint32_t g, uint32_t c, uint32_t k0, uint32_t k1, Row<L> &cur,
-                                          const Row<L> &up, const Row<L> &dn, int &m, const uint32_t *tab) {
+                                          const Row<L> &up, const Row<L> &dn, int &mi, const uint32_t *tab) {
     constexpr int W = (L + 31) / 32;
-    Row<L> xu, xd;
+    Row<L> xu, xd, hb;
+    const Row<L> nx = ring_next<L>(cur);
 #pragma unroll
     for (int w = 0; w < W; ++w) {
         xu.w[w] = cur.w[w] ^ up.w[w];
         xd.w[w] = cur.w[w] ^ dn.w[w];
+        hb.w[w] = cur.w[w] ^ nx.w[w];
     }
+    // site 0: every neighbour is as at row start (its left neighbour L-1 comes last)
+    int anti = (int)(bit_at<L>(xu, 0) + bit_at<L>(xd, 0) + bit_at<L>(hb, 0) + bit_at<L>(hb, L - 1));
+    uint32_t t = tab[mi - anti];
+    int D = 16 - 8 * anti;
+    uint32_t f0 = 0;
+    uint4 rnd = make_uint4(0, 0, 0, 0);
 #pragma unroll
-    for (int q = 0; q < L / 4; ++q) {
-        const uint4 rnd = philox10(make_uint4(y * (uint32_t)(L / 4) + (uint32_t)q, g, c, kDomSweep), k0, k1);
-        attempt<L>(4 * q + 0, rnd.x, cur, xu, xd, m, tab);
-        attempt<L>(4 * q + 1, rnd.y, cur, xu, xd, m, tab);
-        attempt<L>(4 * q + 2, rnd.z, cur, xu, xd, m, tab);
-        attempt<L>(4 * q + 3, rnd.w, cur, xu, xd, m, tab);
+    for (int x = 0; x < L; ++x) {
+        if ((x & 3) == 0)
+            rnd = philox10(make_uint4(y * (uint32_t)(L / 4) + (uint32_t)(x >> 2), g, c, kDomSweep), k0, k1);
+        const uint32_t u = (x & 3) == 0 ? rnd.x : (x & 3) == 1 ? rnd.y : (x & 3) == 2 ? rnd.z : rnd.w;
+        int an0 = 0, an1 = 0;
+        uint32_t t0n = 0, t1n = 0;
+        if (x + 1 < L) {
+            const int xn = x + 1;
+            const uint32_t left = bit_at<L>(hb, x);  // bond (x, x+1) at row start
+            uint32_t right = bit_at<L>(hb, xn);      // bond (x+1, x+2)
+            if (xn == L - 1) right ^= f0;            // its right neighbour is site 0
+            an0 = (int)(bit_at<L>(xu, xn) + bit_at<L>(xd, xn) + right + left);
+            an1 = an0 + 1 - 2 * (int)left;
+            t0n = tab[mi - an0];
+            t1n = tab[mi + D - an1];
+        }
+        const bool acc = u <= t;
+        if (x == 0) f0 = acc ? 1u : 0u;
+        cur.w[x >> 5] ^= (acc ? 1u : 0u) << (x & 31);
+        mi = acc ? mi + D : mi;
+        if (x + 1 < L) {
+            anti = acc ? an1 : an0;
+            t = acc ? t1n : t0n;
+            D = 16 - 8 * anti;
+        }
     }
 }
 
@@ -168,7 +205,7 @@ __global__ __launch_bounds__(64) void k_sweep_lds(SweepParams p) {
     __syncthreads();
 
     if (active) {
-        int m = s.lev[c];
+        int mi = 8 * s.lev[c] + 4;
         const uint32_t g0 = s.ctl->g;
         const uint32_t k0 = s.seed, k1 = (uint32_t)L;
         auto load = [&](int y) {
@@ -187,12 +224,13 @@ __global__ __launch_bounds__(64) void k_sweep_lds(SweepParams p) {
             Row<L> cur = load(0);
             Row<L> dn = load(1);
             for (int y = 0; y < L; ++y) {
-                sweep_row<L>((uint32_t)y, g, (uint32_t)c, k0, k1, cur, up, dn, m, tab);
+                sweep_row<L>((uint32_t)y, g, (uint32_t)c, k0, k1, cur, up, dn, mi, tab);
                 store(y, cur);
                 up = cur;
                 cur = dn;
                 dn = load(y + 2 < L ? y + 2 : y + 2 - L);
             }
+            const int m = mi >> 3;
             const int ev = m - N / 2;
             if (s.trace_bytes == 2)
                 ((int16_t *)p.trace)[(size_t)c * p.M + k] = (int16_t)ev;
@@ -203,7 +241,7 @@ __global__ __launch_bounds__(64) void k_sweep_lds(SweepParams p) {
             else
                 atomicAdd(&p.hist[m >> s.bin_shift], 1);
         }
-        s.lev[c] = m;
+        s.lev[c] = mi >> 3;
     }
     __syncthreads();
     if (active)
@@ -234,7 +272,7 @@ __global__ __launch_bounds__(64) void k_sweep_glb(SweepParams p) {
 #pragma unroll
         for (int w = 0; w < W; ++w) lat[(size_t)(y * W + w) * P + c] = r.w[w];
     };
-    int m = s.lev[c];
+    int mi = 8 * s.lev[c] + 4;
     const uint32_t g0 = s.ctl->g;
     const uint32_t k0 = s.seed, k1 = (uint32_t)L;
     for (int64_t k = 0; k < p.M; ++k) {
@@ -243,12 +281,13 @@ __global__ __launch_bounds__(64) void k_sweep_glb(SweepParams p) {
         Row<L> cur = load(0);
         Row<L> dn = load(1);
         for (int y = 0; y < L; ++y) {
-            sweep_row<L>((uint32_t)y, g, (uint32_t)c, k0, k1, cur, up, dn, m, s.tab);
+            sweep_row<L>((uint32_t)y, g, (uint32_t)c, k0, k1, cur, up, dn, mi, s.tab);
             store(y, cur);
             up = cur;
             cur = dn;
             dn = load(y + 2 < L ? y + 2 : y + 2 - L);
         }
+        const int m = mi >> 3;
         const int ev = m - N / 2;
         if (s.trace_bytes == 2)
             ((int16_t *)p.trace)[(size_t)c * p.M + k] = (int16_t)ev;
@@ -256,7 +295,7 @@ __global__ __launch_bounds__(64) void k_sweep_glb(SweepParams p) {
             ((int32_t *)p.trace)[(size_t)c * p.M + k] = ev;
         atomicAdd(&p.hist[m >> s.bin_shift], 1);
     }
-    s.lev[c] = m;
+    s.lev[c] = mi >> 3;
 }
 
 // Any even L (also L not a multiple of 4): bit-by-bit from global memory.

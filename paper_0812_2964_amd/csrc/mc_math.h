@@ -29,11 +29,12 @@ constexpr uint32_t kDomJoin = 2u;
 __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int i = 0; i < 10; ++i) {
-        const uint32_t hi0 = __umulhi(kPhiloxM0, c.x);
-        const uint32_t lo0 = kPhiloxM0 * c.x;
-        const uint32_t hi1 = __umulhi(kPhiloxM1, c.z);
-        const uint32_t lo1 = kPhiloxM1 * c.z;
-        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        // one 32x32->64 product per lane and word (v_mad_u64_u32)
+        const uint64_t p0 = (uint64_t)kPhiloxM0 * c.x;
+        const uint64_t p1 = (uint64_t)kPhiloxM1 * c.z;
+        // three-input xors as one v_bitop3_b32 each (truth table 0x96 = a ^ b ^ c)
+        c = make_uint4(__builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c.y, k0, 0x96), (uint32_t)p1,
+                       __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c.w, k1, 0x96), (uint32_t)p0);
         k0 += kWeyl0;
         k1 += kWeyl1;
     }
