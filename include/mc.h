@@ -74,6 +74,8 @@ typedef struct {
 
 /* Create a context on the current HIP device for n_sizes (1..16) lattice
    sizes, bound to hip_stream (a hipStream_t; NULL = the null stream).
+   Sizes whose lattices fit in LDS (L <= 64) run batched: one persistent
+   launch sweeps all of them (see mc_get_launch).
    Algorithm step 1: every chain c of every size gets its initial spins
    (s_j = +1 iff bit 31 of the domain-1 word of site j is set), its level is
    computed, ln w is set to 0 (w^(1) = 1, Sec. 3.1), the seam is "none" and the
@@ -81,7 +83,8 @@ typedef struct {
    Errors: MC_EINVAL (sizes), MC_ENODEV (no GPU), MC_ENOMEM, MC_EHIP. */
 mc_status mc_create(const mc_size *sizes, int32_t n_sizes, void *hip_stream, mc_ctx **out);
 
-/* Release everything the context owns (waits for its stream first). NULL is a no-op. */
+/* Release everything the context owns (waits for its stream first). NULL is a
+   no-op; MC_ESTATE while graphs of the context exist. */
 mc_status mc_destroy(mc_ctx *ctx);
 
 /* Number of bins / trace element size in bytes / lattice words per chain of a size. */
@@ -142,6 +145,48 @@ mc_status mc_update_weights(mc_ctx *ctx, int32_t size_idx, int32_t *hist_dev, do
 mc_status mc_get_levels(mc_ctx *ctx, int32_t size_idx, int32_t *levels_host);
 mc_status mc_get_lattice(mc_ctx *ctx, int32_t size_idx, int32_t chain, uint32_t *words_host, int32_t n_words);
 mc_status mc_get_counters(mc_ctx *ctx, int32_t size_idx, int32_t *seam, uint32_t *round, uint32_t *sweep);
+
+/* Read ln w of one size into host memory (n_bins values; synchronising). */
+mc_status mc_get_weights(mc_ctx *ctx, int32_t size_idx, double *lnW_host, int32_t n_bins);
+
+/* Progress of the weight recursion of one size (synchronising; each output may
+   be NULL): updates done, first update (1-based) whose histogram was flat (0 =
+   none yet), flatness of the last update, configurations kept by the joints
+   before the last update. */
+mc_status mc_get_progress(mc_ctx *ctx, int32_t size_idx, int32_t *updates, int32_t *first_flat, int32_t *last_flat,
+                          int64_t *retained_last);
+
+/* Launch configuration.  Chains are independent, so the configuration
+   changes speed only, never results.
+   mc_set_chains_per_block: chains per 64-lane workgroup (1..64) of one size.
+   mc_get_launch: chains per workgroup, kernel kind (0 lattice and thresholds
+   in LDS, 1 lattice in LDS, 2 lattice streamed from global memory, 3 generic
+   bit-by-bit kernel for L not among the compiled sizes) and whether the sizes
+   run batched in one persistent launch (all sizes keep lattices in LDS).
+   mc_autotune: times probe_sweeps sweeps of every size on copies of the chain
+   state for 16, 32 and 64 chains per workgroup and keeps the fastest
+   (chains_per_block_out: n_sizes values, nullable).  The chains are not
+   advanced.  Both setters fail with MC_ESTATE while graphs of the context
+   exist. */
+mc_status mc_set_chains_per_block(mc_ctx *ctx, int32_t size_idx, int32_t chains_per_block);
+mc_status mc_get_launch(mc_ctx *ctx, int32_t size_idx, int32_t *chains_per_block, int32_t *kind, int32_t *batched);
+mc_status mc_autotune(mc_ctx *ctx, int64_t probe_sweeps, int32_t *chains_per_block_out);
+
+/* A captured sequence of n_iters whole iterations of the method for every
+   size of the context -- mc_run_chains, mc_join and mc_update_weights, as in
+   Sec. 4.2 -- replayed with one call (HIP graph).  The counters of the chains
+   live in device memory, so every replay continues the recursion.  The
+   buffers (host arrays of n_sizes device pointers, shapes as for the single
+   calls) are baked into the graph and must stay allocated; hist_dev must hold
+   zeros before the first replay (each update leaves them zeroed).  A graph
+   can only be created and launched right after a weight update (or at the
+   start).  Destroy graphs before their context.
+   Errors: MC_EINVAL, MC_ESTATE, MC_EOVERFLOW (n_chains * n_sweeps >= 2^31). */
+typedef struct mc_graph mc_graph;
+mc_status mc_graph_create(mc_ctx *ctx, int64_t n_sweeps, int32_t n_iters, void *const *trace_dev,
+                          int32_t *const *hist_dev, int32_t *const *cut_dev, int32_t mode, mc_graph **out);
+mc_status mc_graph_launch(mc_ctx *ctx, mc_graph *graph);
+mc_status mc_graph_destroy(mc_graph *graph);
 
 /* Wait for all work of the context. */
 mc_status mc_sync(mc_ctx *ctx);

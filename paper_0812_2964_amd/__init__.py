@@ -22,7 +22,8 @@ _STATUS = {0: "MC_OK", -1: "MC_EINVAL", -2: "MC_ENOMEM", -3: "MC_ENODEV", -4: "M
 # Symbols declared in include/mc.h (checked by the CPU test-suite).
 EXPORTED = ["mc_create", "mc_destroy", "mc_n_bins", "mc_trace_elem_bytes", "mc_lattice_words", "mc_init_weights",
             "mc_run_chains", "mc_join", "mc_update_weights", "mc_get_levels", "mc_get_lattice", "mc_get_counters",
-            "mc_sync", "mc_last_error"]
+            "mc_get_weights", "mc_get_progress", "mc_set_chains_per_block", "mc_get_launch", "mc_autotune",
+            "mc_graph_create", "mc_graph_launch", "mc_graph_destroy", "mc_sync", "mc_last_error"]
 
 
 class MCError(RuntimeError):
@@ -63,6 +64,14 @@ def lib():
     L.mc_get_levels.argtypes = [p, i32, p]
     L.mc_get_lattice.argtypes = [p, i32, i32, p, i32]
     L.mc_get_counters.argtypes = [p, i32, p, p, p]
+    L.mc_get_weights.argtypes = [p, i32, p, i32]
+    L.mc_get_progress.argtypes = [p, i32, p, p, p, p]
+    L.mc_set_chains_per_block.argtypes = [p, i32, i32]
+    L.mc_get_launch.argtypes = [p, i32, p, p, p]
+    L.mc_autotune.argtypes = [p, i64, p]
+    L.mc_graph_create.argtypes = [p, i64, i32, p, p, p, i32, ctypes.POINTER(p)]
+    L.mc_graph_launch.argtypes = [p, p]
+    L.mc_graph_destroy.argtypes = [p]
     L.mc_sync.argtypes = [p]
     L.mc_last_error.restype = ctypes.c_char_p
     for f in EXPORTED:
@@ -109,7 +118,7 @@ class Context:
 
     def close(self):
         if getattr(self, "_h", None):
-            lib().mc_destroy(self._h)
+            _check(lib().mc_destroy(self._h))  # refuses while graphs of the context exist
             self._h = None
 
     def __del__(self):
@@ -224,5 +233,72 @@ class Context:
         _check(lib().mc_get_counters(self._h, i, ctypes.byref(seam), ctypes.byref(rnd), ctypes.byref(sw)))
         return seam.value, rnd.value, sw.value
 
+    def weights(self, i=0):
+        w = np.zeros(self.n_bins(i), dtype=np.float64)
+        _check(lib().mc_get_weights(self._h, i, w.ctypes.data_as(ctypes.c_void_p), self.n_bins(i)))
+        return w
+
+    def progress(self, i=0):
+        """(updates done, first flat update or 0, last update flat, kept before last update)"""
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        r = ctypes.c_int64()
+        _check(lib().mc_get_progress(self._h, i, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(r)))
+        return a.value, b.value, bool(c.value), r.value
+
+    # -- launch configuration (speed only, never results) ------------------
+    def set_chains_per_block(self, cpb, i=0):
+        _check(lib().mc_set_chains_per_block(self._h, i, int(cpb)))
+
+    def launch(self, i=0):
+        """(chains per block, kernel kind, batched flag)"""
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().mc_get_launch(self._h, i, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, bool(c.value)
+
+    def autotune(self, probe_sweeps=20):
+        out = (ctypes.c_int32 * len(self.sizes))()
+        _check(lib().mc_autotune(self._h, int(probe_sweeps), out))
+        return list(out)
+
+    def graph(self, n_sweeps, n_iters, traces, hists, cuts, mode=0):
+        return Graph(self, n_sweeps, n_iters, traces, hists, cuts, mode)
+
     def sync(self):
         _check(lib().mc_sync(self._h))
+
+
+class Graph:
+    """n_iters captured iterations (run + join + update of every size)."""
+
+    def __init__(self, ctx, n_sweeps, n_iters, traces, hists, cuts, mode=0):
+        import torch
+
+        n = len(ctx.sizes)
+        if not (len(traces) == len(hists) == len(cuts) == n):
+            raise ValueError("need one trace, hist and cut buffer per size")
+        tp = (ctypes.c_void_p * n)()
+        hp = (ctypes.c_void_p * n)()
+        cp = (ctypes.c_void_p * n)()
+        for i in range(n):
+            tp[i] = _dev_ptr(traces[i], ctx.trace_dtype(i), ctx.sizes[i][1] * n_sweeps, "trace").value
+            hp[i] = _dev_ptr(hists[i], torch.int32, ctx.n_bins(i), "hist").value
+            cp[i] = _dev_ptr(cuts[i], torch.int32, ctx.sizes[i][1], "cut").value
+        self._keep = (traces, hists, cuts)  # the graph reads and writes these buffers
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        _check(lib().mc_graph_create(ctx._h, int(n_sweeps), int(n_iters), tp, hp, cp, int(mode), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self):
+        _check(lib().mc_graph_launch(self.ctx._h, self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mc_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -30,6 +31,7 @@ mc_status fail(mc_status st, const char *fmt, ...) {
 struct HostSize {
     mc_size cfg;
     SizeDev dev;
+    SizePlan plan;     // how its sweeps are launched
     int64_t pending;   // configurations added to histograms since the last update
     int64_t last_M;    // sweeps of the last mc_run_chains, 0 after its joint
 };
@@ -38,10 +40,25 @@ struct HostSize {
 
 struct mc_ctx {
     int device = 0;
+    int n_cu = 256;
     hipStream_t stream = nullptr;
+    hipStream_t capture_stream = nullptr;  // created on first graph capture
     bool broken = false;
-    int chains_per_block = 64;
     std::vector<HostSize> sizes;
+    // batched launch of all sizes (when every size keeps its lattices in LDS)
+    bool batched = false;
+    Tile *tiles_dev = nullptr;
+    int32_t *counter_dev = nullptr;
+    int n_tiles = 0;
+    int batch_grid = 0;
+    size_t batch_lds = 0;
+    int live_graphs = 0;  // graphs hold the tile buffer and the state pointers
+};
+
+struct mc_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    mc_ctx *ctx = nullptr;
 };
 
 namespace {
@@ -80,6 +97,75 @@ void free_size(SizeDev &d) {
     d = SizeDev{};
 }
 
+// Default chains per block: as many as fit with the thresholds in LDS.
+SizePlan default_plan(const SizeDev &d) {
+    SizePlan p = plan_sweeps(d, 64);
+    for (int cpb = 32; p.kind == kSweepLds && cpb >= 16; cpb /= 2) {
+        SizePlan q = plan_sweeps(d, cpb);
+        if (q.kind == kSweepLdsTab) p = q;
+    }
+    return p;
+}
+
+// (Re)build the launch configuration after the plans changed.  Not allowed
+// while capturing (it copies to the device and sets kernel attributes).
+hipError_t rebuild_launch(mc_ctx *ctx) {
+    for (auto &h : ctx->sizes) {
+        hipError_t e = prepare_sweeps(h.dev, h.plan);
+        if (e != hipSuccess) return e;
+    }
+    ctx->batched = ctx->sizes.size() > 1;
+    for (auto &h : ctx->sizes) ctx->batched = ctx->batched && batchable(h.plan);
+    if (!ctx->batched) return hipSuccess;
+    // tiles, largest lattice first so the longest work starts first
+    std::vector<int> order(ctx->sizes.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return ctx->sizes[a].dev.N > ctx->sizes[b].dev.N; });
+    std::vector<Tile> tiles;
+    size_t lds = 0;
+    for (int i : order) {
+        const HostSize &h = ctx->sizes[i];
+        for (int c0 = 0; c0 < h.dev.P; c0 += h.plan.cpb) tiles.push_back(Tile{i, c0});
+        lds = std::max(lds, h.plan.lds_bytes);
+    }
+    if (ctx->tiles_dev) (void)hipFree(ctx->tiles_dev);
+    ctx->tiles_dev = nullptr;
+    hipError_t e = hipMalloc((void **)&ctx->tiles_dev, tiles.size() * sizeof(Tile));
+    if (e != hipSuccess) return e;
+    e = hipMemcpy(ctx->tiles_dev, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return e;
+    if (!ctx->counter_dev) {
+        e = hipMalloc((void **)&ctx->counter_dev, sizeof(int32_t));
+        if (e != hipSuccess) return e;
+    }
+    ctx->n_tiles = (int)tiles.size();
+    ctx->batch_lds = lds;
+    const int per_cu = std::max(1, (int)((160 * 1024) / std::max<size_t>(lds, 1)));
+    ctx->batch_grid = std::min(ctx->n_tiles, ctx->n_cu * std::min(per_cu, 8));
+    return prepare_batched(lds);
+}
+
+// Sweeps of every size (Algorithm step 2), one launch when batched.
+hipError_t enqueue_sweeps(mc_ctx *ctx, hipStream_t st, int64_t M, void *const *trace, int32_t *const *hist) {
+    const int n = (int)ctx->sizes.size();
+    hipError_t e = hipSuccess;
+    if (ctx->batched) {
+        std::vector<SizeDev> devs(n);
+        std::vector<SizePlan> plans(n);
+        for (int i = 0; i < n; ++i) {
+            devs[i] = ctx->sizes[i].dev;
+            plans[i] = ctx->sizes[i].plan;
+        }
+        e = launch_sweeps_batched(devs.data(), plans.data(), n, ctx->tiles_dev, ctx->n_tiles, ctx->counter_dev,
+                                  ctx->batch_grid, ctx->batch_lds, M, trace, hist, st);
+    } else {
+        for (int i = 0; i < n && e == hipSuccess; ++i)
+            e = launch_sweeps(ctx->sizes[i].dev, ctx->sizes[i].plan, M, trace[i], hist[i], st);
+    }
+    for (int i = 0; i < n && e == hipSuccess; ++i) e = launch_advance(ctx->sizes[i].dev, M, st);
+    return e;
+}
+
 }  // namespace
 
 extern "C" {
@@ -108,6 +194,9 @@ mc_status mc_create(const mc_size *sizes, int32_t n_sizes, void *hip_stream, mc_
         delete ctx;
         return fail(MC_ENODEV, "hipGetDevice failed");
     }
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device) == hipSuccess && ncu > 0)
+        ctx->n_cu = ncu;
     ctx->sizes.resize(n_sizes);
     mc_status st = MC_OK;
     for (int i = 0; i < n_sizes && st == MC_OK; ++i) {
@@ -145,9 +234,16 @@ mc_status mc_create(const mc_size *sizes, int32_t n_sizes, void *hip_stream, mc_
         if (e == hipSuccess) e = launch_tabulate(d, ctx->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
         if (e != hipSuccess) st = hip_fail(nullptr, e, "context initialisation");
+        h.plan = default_plan(d);
+    }
+    if (st == MC_OK) {
+        hipError_t e = rebuild_launch(ctx);
+        if (e != hipSuccess) st = hip_fail(nullptr, e, "launch configuration");
     }
     if (st != MC_OK) {
         for (auto &h : ctx->sizes) free_size(h.dev);
+        if (ctx->tiles_dev) (void)hipFree(ctx->tiles_dev);
+        if (ctx->counter_dev) (void)hipFree(ctx->counter_dev);
         delete ctx;
         return st;
     }
@@ -157,8 +253,12 @@ mc_status mc_create(const mc_size *sizes, int32_t n_sizes, void *hip_stream, mc_
 
 mc_status mc_destroy(mc_ctx *ctx) {
     if (!ctx) return MC_OK;
+    if (ctx->live_graphs > 0) return fail(MC_ESTATE, "destroy the context's graphs first");
     (void)hipStreamSynchronize(ctx->stream);
     for (auto &h : ctx->sizes) free_size(h.dev);
+    if (ctx->tiles_dev) (void)hipFree(ctx->tiles_dev);
+    if (ctx->counter_dev) (void)hipFree(ctx->counter_dev);
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     delete ctx;
     return MC_OK;
 }
@@ -202,7 +302,6 @@ mc_status mc_run_chains(mc_ctx *ctx, int64_t n_sweeps, void *const *trace_dev, i
     if (n_sweeps < 1 || n_sweeps > 0x7FFFFFFF) return fail(MC_EINVAL, "n_sweeps=%lld must be 1..2^31-1", (long long)n_sweeps);
     if (!trace_dev || !hist_dev) return fail(MC_EINVAL, "null trace/hist pointer array");
     const int n = (int)ctx->sizes.size();
-    std::vector<SizeDev> devs(n);
     for (int i = 0; i < n; ++i) {
         HostSize &h = ctx->sizes[i];
         if (!trace_dev[i] || !hist_dev[i]) return fail(MC_EINVAL, "size %d: null trace or hist", i);
@@ -210,9 +309,8 @@ mc_status mc_run_chains(mc_ctx *ctx, int64_t n_sweeps, void *const *trace_dev, i
         if (h.pending + add > 0x7FFFFFFFll)
             return fail(MC_EOVERFLOW, "size %d: %lld configurations would exceed the int32 histogram", i,
                         (long long)(h.pending + add));
-        devs[i] = h.dev;
     }
-    HIP_OR_FAIL(ctx, launch_sweeps(devs.data(), n, n_sweeps, trace_dev, hist_dev, ctx->chains_per_block, ctx->stream));
+    HIP_OR_FAIL(ctx, enqueue_sweeps(ctx, ctx->stream, n_sweeps, trace_dev, hist_dev));
     for (int i = 0; i < n; ++i) {
         ctx->sizes[i].pending += (int64_t)ctx->sizes[i].dev.P * n_sweeps;
         ctx->sizes[i].last_M = n_sweeps;
@@ -295,6 +393,190 @@ mc_status mc_sync(mc_ctx *ctx) {
     mc_status st = check_ctx(ctx);
     if (st != MC_OK) return st;
     HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+    return MC_OK;
+}
+
+mc_status mc_get_weights(mc_ctx *ctx, int32_t i, double *lnW_host, int32_t n_bins) {
+    mc_status st = check_size(ctx, i);
+    if (st != MC_OK) return st;
+    const SizeDev &d = ctx->sizes[i].dev;
+    if (!lnW_host || n_bins != d.n_bins) return fail(MC_EINVAL, "need %d bins", d.n_bins);
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(lnW_host, d.lnW, (size_t)d.n_bins * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+    return MC_OK;
+}
+
+mc_status mc_get_progress(mc_ctx *ctx, int32_t i, int32_t *updates, int32_t *first_flat, int32_t *last_flat,
+                          int64_t *retained_last) {
+    mc_status st = check_size(ctx, i);
+    if (st != MC_OK) return st;
+    Ctl c{};
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(&c, ctx->sizes[i].dev.ctl, sizeof c, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+    if (updates) *updates = c.iter;
+    if (first_flat) *first_flat = c.flat_iter;
+    if (last_flat) *last_flat = c.flat;
+    if (retained_last) *retained_last = c.retained_last;
+    return MC_OK;
+}
+
+mc_status mc_set_chains_per_block(mc_ctx *ctx, int32_t i, int32_t chains_per_block) {
+    mc_status st = check_size(ctx, i);
+    if (st != MC_OK) return st;
+    if (chains_per_block < 1 || chains_per_block > 64) return fail(MC_EINVAL, "chains_per_block must be 1..64");
+    if (ctx->live_graphs > 0) return fail(MC_ESTATE, "the launch configuration is fixed while graphs exist");
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->sizes[i].plan = plan_sweeps(ctx->sizes[i].dev, chains_per_block);
+    HIP_OR_FAIL(ctx, rebuild_launch(ctx));
+    return MC_OK;
+}
+
+mc_status mc_get_launch(mc_ctx *ctx, int32_t i, int32_t *chains_per_block, int32_t *kind, int32_t *batched) {
+    mc_status st = check_size(ctx, i);
+    if (st != MC_OK) return st;
+    if (chains_per_block) *chains_per_block = ctx->sizes[i].plan.cpb;
+    if (kind) *kind = ctx->sizes[i].plan.kind;
+    if (batched) *batched = ctx->batched ? 1 : 0;
+    return MC_OK;
+}
+
+mc_status mc_autotune(mc_ctx *ctx, int64_t probe_sweeps, int32_t *chains_per_block_out) {
+    mc_status st = check_ctx(ctx);
+    if (st != MC_OK) return st;
+    if (probe_sweeps < 1 || probe_sweeps > 100000) return fail(MC_EINVAL, "probe_sweeps must be 1..100000");
+    if (ctx->live_graphs > 0) return fail(MC_ESTATE, "the launch configuration is fixed while graphs exist");
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+    hipEvent_t e0, e1;
+    HIP_OR_FAIL(ctx, hipEventCreate(&e0));
+    HIP_OR_FAIL(ctx, hipEventCreate(&e1));
+    const int cands[3] = {16, 32, 64};
+    hipError_t e = hipSuccess;
+    for (size_t i = 0; i < ctx->sizes.size() && e == hipSuccess; ++i) {
+        HostSize &h = ctx->sizes[i];
+        const SizeDev &d = h.dev;
+        // probes run on copies of the chain state, so the chains are untouched
+        SizeDev scr = d;
+        scr.lat = nullptr;
+        scr.lev = nullptr;
+        scr.ctl = nullptr;
+        void *tr = nullptr;
+        int32_t *hs = nullptr;
+        const size_t lat_b = (size_t)d.L * d.W * d.P * 4;
+        e = hipMalloc((void **)&scr.lat, lat_b);
+        if (e == hipSuccess) e = hipMalloc((void **)&scr.lev, (size_t)d.P * 4);
+        if (e == hipSuccess) e = hipMalloc((void **)&scr.ctl, sizeof(Ctl));
+        if (e == hipSuccess) e = hipMalloc(&tr, (size_t)d.P * probe_sweeps * d.trace_bytes);
+        if (e == hipSuccess) e = hipMalloc((void **)&hs, (size_t)d.n_bins * 4);
+        float best = 1e30f;
+        SizePlan best_plan = h.plan;
+        for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+            const SizePlan cand = plan_sweeps(d, cands[k]);
+            if (cand.kind == kSweepGeneric) break;
+            e = prepare_sweeps(d, cand);
+            float t_min = 1e30f;
+            for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+                e = hipMemcpyAsync(scr.lat, d.lat, lat_b, hipMemcpyDeviceToDevice, ctx->stream);
+                if (e == hipSuccess) e = hipMemcpyAsync(scr.lev, d.lev, (size_t)d.P * 4, hipMemcpyDeviceToDevice, ctx->stream);
+                if (e == hipSuccess) e = hipMemcpyAsync(scr.ctl, d.ctl, sizeof(Ctl), hipMemcpyDeviceToDevice, ctx->stream);
+                if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
+                if (e == hipSuccess) e = launch_sweeps(scr, cand, probe_sweeps, tr, hs, ctx->stream);
+                if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                t_min = std::min(t_min, ms);
+            }
+            if (e == hipSuccess && t_min < best) {
+                best = t_min;
+                best_plan = cand;
+            }
+        }
+        if (scr.lat) (void)hipFree(scr.lat);
+        if (scr.lev) (void)hipFree(scr.lev);
+        if (scr.ctl) (void)hipFree(scr.ctl);
+        if (tr) (void)hipFree(tr);
+        if (hs) (void)hipFree(hs);
+        if (e == hipSuccess) h.plan = best_plan;
+        if (chains_per_block_out) chains_per_block_out[i] = h.plan.cpb;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(ctx, e, "autotune");
+    HIP_OR_FAIL(ctx, rebuild_launch(ctx));
+    return MC_OK;
+}
+
+mc_status mc_graph_create(mc_ctx *ctx, int64_t n_sweeps, int32_t n_iters, void *const *trace_dev,
+                          int32_t *const *hist_dev, int32_t *const *cut_dev, int32_t mode, mc_graph **out) {
+    if (!out) return fail(MC_EINVAL, "null output pointer");
+    *out = nullptr;
+    mc_status st = check_ctx(ctx);
+    if (st != MC_OK) return st;
+    if (n_sweeps < 1 || n_sweeps > 0x7FFFFFFF) return fail(MC_EINVAL, "n_sweeps must be 1..2^31-1");
+    if (n_iters < 1 || n_iters > 100000) return fail(MC_EINVAL, "n_iters must be 1..100000");
+    if (mode != 0 && mode != 1) return fail(MC_EINVAL, "mode must be 0 or 1");
+    if (!trace_dev || !hist_dev || !cut_dev) return fail(MC_EINVAL, "null pointer array");
+    const int n = (int)ctx->sizes.size();
+    for (int i = 0; i < n; ++i) {
+        const HostSize &h = ctx->sizes[i];
+        if (!trace_dev[i] || !hist_dev[i] || !cut_dev[i]) return fail(MC_EINVAL, "size %d: null buffer", i);
+        if (h.pending != 0 || h.last_M != 0)
+            return fail(MC_ESTATE, "size %d: a graph must start after a weight update", i);
+        if ((int64_t)h.dev.P * n_sweeps > 0x7FFFFFFFll)
+            return fail(MC_EOVERFLOW, "size %d: one iteration exceeds the int32 histogram", i);
+    }
+    if (!ctx->capture_stream)
+        HIP_OR_FAIL(ctx, hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+    hipStream_t cs = ctx->capture_stream;
+    HIP_OR_FAIL(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int it = 0; it < n_iters && e == hipSuccess; ++it) {
+        e = enqueue_sweeps(ctx, cs, n_sweeps, trace_dev, hist_dev);
+        for (int i = 0; i < n && e == hipSuccess; ++i)
+            e = launch_join(ctx->sizes[i].dev, trace_dev[i], n_sweeps, cut_dev[i], hist_dev[i], mode, cs);
+        for (int i = 0; i < n && e == hipSuccess; ++i) e = launch_update(ctx->sizes[i].dev, hist_dev[i], cs);
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t e_end = hipStreamEndCapture(cs, &graph);
+    if (e == hipSuccess) e = e_end;
+    if (e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return hip_fail(ctx, e, "graph capture");
+    }
+    mc_graph *g = new mc_graph();
+    g->graph = graph;
+    g->ctx = ctx;
+    e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        delete g;
+        return hip_fail(ctx, e, "graph instantiation");
+    }
+    ctx->live_graphs += 1;
+    *out = g;
+    return MC_OK;
+}
+
+mc_status mc_graph_launch(mc_ctx *ctx, mc_graph *g) {
+    mc_status st = check_ctx(ctx);
+    if (st != MC_OK) return st;
+    if (!g || g->ctx != ctx) return fail(MC_EINVAL, "graph does not belong to this context");
+    for (const auto &h : ctx->sizes)
+        if (h.pending != 0 || h.last_M != 0) return fail(MC_ESTATE, "a graph must start after a weight update");
+    HIP_OR_FAIL(ctx, hipGraphLaunch(g->exec, ctx->stream));
+    return MC_OK;
+}
+
+mc_status mc_graph_destroy(mc_graph *g) {
+    if (!g) return MC_OK;
+    if (g->ctx) {
+        (void)hipStreamSynchronize(g->ctx->stream);
+        g->ctx->live_graphs -= 1;
+    }
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
     return MC_OK;
 }
 

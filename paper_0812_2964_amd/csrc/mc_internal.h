@@ -33,12 +33,41 @@ struct SizeDev {
     int32_t *scratch_cut;   // [P] speculative cut points of the joint
 };
 
+// How the sweeps of one size are launched.
+enum SweepKind : int32_t {
+    kSweepLdsTab = 0,   // lattice and thresholds in LDS
+    kSweepLds = 1,      // lattice in LDS, thresholds read from global memory
+    kSweepGlobal = 2,   // lattice rows streamed from global memory (large L)
+    kSweepGeneric = 3,  // any even L, bit by bit (L not among the compiled sizes)
+};
+
+struct SizePlan {
+    int32_t cpb;        // chains per 64-lane block
+    int32_t kind;       // SweepKind
+    size_t lds_bytes;   // dynamic LDS per block
+};
+
+constexpr int kMaxSizes = 16;
+
+// One unit of work of the batched launch: chains c0 .. c0+cpb-1 of size `size`.
+struct Tile {
+    int32_t size;
+    int32_t c0;
+};
+
 // Kernel launchers (mc_kernels.hip).  All enqueue on `st` and return the
 // launch status.
+SizePlan plan_sweeps(const SizeDev &s, int chains_per_block);
+bool batchable(const SizePlan &p);
+hipError_t prepare_sweeps(const SizeDev &s, const SizePlan &p);  // kernel attributes; call outside capture
+hipError_t prepare_batched(size_t lds_bytes);
 hipError_t launch_init(const SizeDev &s, hipStream_t st);
 hipError_t launch_tabulate(const SizeDev &s, hipStream_t st);
-hipError_t launch_sweeps(const SizeDev *sizes, int n_sizes, int64_t M, void *const *trace, int32_t *const *hist,
-                         int chains_per_block, hipStream_t st);
+hipError_t launch_sweeps(const SizeDev &s, const SizePlan &p, int64_t M, void *trace, int32_t *hist, hipStream_t st);
+hipError_t launch_sweeps_batched(const SizeDev *sizes, const SizePlan *plans, int n_sizes, const Tile *tiles_dev,
+                                 int n_tiles, int32_t *counter_dev, int grid, size_t lds_bytes, int64_t M,
+                                 void *const *trace, int32_t *const *hist, hipStream_t st);
+hipError_t launch_advance(const SizeDev &s, int64_t M, hipStream_t st);
 hipError_t launch_join(const SizeDev &s, const void *trace, int64_t M, int32_t *cut, int32_t *hist, int mode,
                        hipStream_t st);
 hipError_t launch_update(const SizeDev &s, int32_t *hist, hipStream_t st);

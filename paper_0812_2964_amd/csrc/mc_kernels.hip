@@ -178,19 +178,19 @@ __device__ __forceinline__ void sweep_row(uint32_t y, uint32_t g, uint32_t c, ui
     }
 }
 
-// Lattice and (optionally) thresholds in LDS.  LDS layout:
+// Sweeps of the chains c0 .. c0+cpb-1 of one size, lane l = chain c0 + l,
+// with the lattices and (TAB_LDS) the thresholds held in LDS.  LDS layout:
 //   [L*W*cpb] lattice words, word (row*W + w) of local chain l at (row*W+w)*cpb + l
 //   [(N+1)*8] thresholds           (TAB_LDS)
 //   [n_bins]  histogram            (lds_hist)
+// Must be called by all 64 threads of the block (it synchronises).
 template <int L, bool TAB_LDS>
-__global__ __launch_bounds__(64) void k_sweep_lds(SweepParams p) {
+__device__ __forceinline__ void sweep_tile_lds(const SizeDev &s, int c0, int cpb, int64_t M, void *trace,
+                                               int32_t *hist, bool lds_hist, uint32_t *smem) {
     constexpr int W = (L + 31) / 32;
     constexpr int N = L * L;
-    extern __shared__ uint32_t smem[];
-    const SizeDev &s = p.s;
-    const int cpb = p.cpb;
     const int lane = threadIdx.x;
-    const int c = blockIdx.x * cpb + lane;
+    const int c = c0 + lane;
     const bool active = lane < cpb && c < s.P;
     uint32_t *slat = smem;
     uint32_t *stab = smem + L * W * cpb;
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(64) void k_sweep_lds(SweepParams p) {
     const uint32_t *tab = TAB_LDS ? stab : s.tab;
     if (TAB_LDS)
         for (int i = lane; i < (N + 1) * 8; i += blockDim.x) stab[i] = s.tab[i];
-    if (p.lds_hist)
+    if (lds_hist)
         for (int i = lane; i < s.n_bins; i += blockDim.x) shist[i] = 0;
     if (active)
         for (int w = 0; w < L * W; ++w) slat[w * cpb + lane] = s.lat[(size_t)w * s.P + c];
@@ -218,7 +218,7 @@ __global__ __launch_bounds__(64) void k_sweep_lds(SweepParams p) {
 #pragma unroll
             for (int w = 0; w < W; ++w) slat[(y * W + w) * cpb + lane] = r.w[w];
         };
-        for (int64_t k = 0; k < p.M; ++k) {
+        for (int64_t k = 0; k < M; ++k) {
             const uint32_t g = g0 + (uint32_t)k;
             Row<L> up = load(L - 1);
             Row<L> cur = load(0);
@@ -233,22 +233,29 @@ __global__ __launch_bounds__(64) void k_sweep_lds(SweepParams p) {
             const int m = mi >> 3;
             const int ev = m - N / 2;
             if (s.trace_bytes == 2)
-                ((int16_t *)p.trace)[(size_t)c * p.M + k] = (int16_t)ev;
+                ((int16_t *)trace)[(size_t)c * M + k] = (int16_t)ev;
             else
-                ((int32_t *)p.trace)[(size_t)c * p.M + k] = ev;
-            if (p.lds_hist)
+                ((int32_t *)trace)[(size_t)c * M + k] = ev;
+            if (lds_hist)
                 atomicAdd(&shist[m >> s.bin_shift], 1);
             else
-                atomicAdd(&p.hist[m >> s.bin_shift], 1);
+                atomicAdd(&hist[m >> s.bin_shift], 1);
         }
         s.lev[c] = mi >> 3;
     }
     __syncthreads();
     if (active)
         for (int w = 0; w < L * W; ++w) s.lat[(size_t)w * s.P + c] = slat[w * cpb + lane];
-    if (p.lds_hist)
+    if (lds_hist)
         for (int i = lane; i < s.n_bins; i += blockDim.x)
-            if (shist[i]) atomicAdd(&p.hist[i], shist[i]);
+            if (shist[i]) atomicAdd(&hist[i], shist[i]);
+    __syncthreads();
+}
+
+template <int L, bool TAB_LDS>
+__global__ __launch_bounds__(64) void k_sweep_lds(SweepParams p) {
+    extern __shared__ uint32_t smem[];
+    sweep_tile_lds<L, TAB_LDS>(p.s, blockIdx.x * p.cpb, p.cpb, p.M, p.trace, p.hist, p.lds_hist != 0, smem);
 }
 
 // Lattice rows streamed from global memory (large L); thresholds from global.
@@ -338,31 +345,77 @@ __global__ __launch_bounds__(64) void k_sweep_generic(SweepParams p) {
 
 __global__ void k_advance_sweeps(Ctl *ctl, uint32_t M) { ctl->g += M; }
 
+hipError_t launch_advance(const SizeDev &s, int64_t M, hipStream_t st) {
+    hipLaunchKernelGGL(k_advance_sweeps, dim3(1), dim3(1), 0, st, s.ctl, (uint32_t)M);
+    return hipGetLastError();
+}
+
+// Dynamic LDS a launch may use: a CU's 160 KB less room for the kernels'
+// static LDS.
+constexpr size_t kLdsMax = 160 * 1024 - 256;
+
+static bool compiled_size(int L) {
+    switch (L) {
+    case 4: case 8: case 12: case 16: case 20: case 24: case 32: case 40: case 48: case 64: case 128: case 256:
+        return true;
+    default:
+        return false;
+    }
+}
+
+SizePlan plan_sweeps(const SizeDev &s, int cpb) {
+    SizePlan p{};
+    p.cpb = cpb < 1 ? 1 : (cpb > 64 ? 64 : cpb);
+    if (!compiled_size(s.L)) {
+        p.kind = kSweepGeneric;
+        p.cpb = 64;
+        return p;
+    }
+    const size_t lat_b = (size_t)s.L * s.W * p.cpb * 4;
+    const size_t tab_b = (size_t)(s.N + 1) * 8 * 4;
+    const size_t hist_b = (size_t)s.n_bins * 4;
+    if (s.L <= 64 && lat_b + tab_b + hist_b <= kLdsMax) {
+        p.kind = kSweepLdsTab;
+        p.lds_bytes = lat_b + tab_b + hist_b;
+    } else if (s.L <= 64 && lat_b + hist_b <= kLdsMax) {
+        p.kind = kSweepLds;
+        p.lds_bytes = lat_b + hist_b;
+    } else {
+        p.kind = kSweepGlobal;
+        p.lds_bytes = 0;
+    }
+    return p;
+}
+
+bool batchable(const SizePlan &p) { return p.kind == kSweepLdsTab || p.kind == kSweepLds; }
+
+// Raise a kernel's dynamic-LDS limit to at least `bytes` (never lower it: one
+// kernel can serve several sizes with different plans).
+static hipError_t allow_lds(const void *kernel, size_t &allowed, size_t bytes) {
+    if (bytes <= allowed) return hipSuccess;
+    const hipError_t e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess) allowed = bytes;
+    return e;
+}
+
 template <int L>
-static hipError_t launch_sweep_L(const SweepParams &p0, hipStream_t st) {
-    constexpr int W = (L + 31) / 32;
-    constexpr int N = L * L;
+static hipError_t prepare_L(const SizePlan &p) {
+    static size_t allowed_tab = 0, allowed_notab = 0;
+    if (p.kind == kSweepLdsTab) return allow_lds((const void *)k_sweep_lds<L, true>, allowed_tab, p.lds_bytes);
+    if (p.kind == kSweepLds) return allow_lds((const void *)k_sweep_lds<L, false>, allowed_notab, p.lds_bytes);
+    return hipSuccess;
+}
+
+template <int L>
+static hipError_t launch_L(const SweepParams &p0, const SizePlan &pl, hipStream_t st) {
     SweepParams p = p0;
-    const int cpb = p.cpb;
-    const size_t lat_b = (size_t)L * W * cpb * 4;
-    const size_t tab_b = (size_t)(N + 1) * 8 * 4;
-    const size_t hist_b = (size_t)p.s.n_bins * 4;
-    const size_t lds_max = 160 * 1024;
-    const dim3 grid((p.s.P + cpb - 1) / cpb), block(64);
-    if (L <= 64 && lat_b + tab_b + hist_b <= lds_max) {
+    const dim3 grid((p.s.P + pl.cpb - 1) / pl.cpb), block(64);
+    if (pl.kind == kSweepLdsTab) {
         p.lds_hist = 1;
-        const size_t bytes = lat_b + tab_b + hist_b;
-        auto kern = k_sweep_lds<L, true>;
-        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(kern, grid, block, bytes, st, p);
-    } else if (L <= 64 && lat_b + hist_b <= lds_max) {
+        hipLaunchKernelGGL((k_sweep_lds<L, true>), grid, block, pl.lds_bytes, st, p);
+    } else if (pl.kind == kSweepLds) {
         p.lds_hist = 1;
-        const size_t bytes = lat_b + hist_b;
-        auto kern = k_sweep_lds<L, false>;
-        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(kern, grid, block, bytes, st, p);
+        hipLaunchKernelGGL((k_sweep_lds<L, false>), grid, block, pl.lds_bytes, st, p);
     } else {
         p.lds_hist = 0;
         hipLaunchKernelGGL(k_sweep_glb<L>, grid, block, 0, st, p);
@@ -370,40 +423,118 @@ static hipError_t launch_sweep_L(const SweepParams &p0, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_sweeps(const SizeDev *sizes, int n_sizes, int64_t M, void *const *trace, int32_t *const *hist,
-                         int chains_per_block, hipStream_t st) {
-    for (int i = 0; i < n_sizes; ++i) {
-        SweepParams p{};
-        p.s = sizes[i];
-        p.M = M;
-        p.trace = trace[i];
-        p.hist = hist[i];
-        p.cpb = chains_per_block;
-        p.lds_hist = 0;
-        hipError_t e = hipSuccess;
-        switch (p.s.L) {
-        case 4: e = launch_sweep_L<4>(p, st); break;
-        case 8: e = launch_sweep_L<8>(p, st); break;
-        case 12: e = launch_sweep_L<12>(p, st); break;
-        case 16: e = launch_sweep_L<16>(p, st); break;
-        case 20: e = launch_sweep_L<20>(p, st); break;
-        case 24: e = launch_sweep_L<24>(p, st); break;
-        case 32: e = launch_sweep_L<32>(p, st); break;
-        case 40: e = launch_sweep_L<40>(p, st); break;
-        case 48: e = launch_sweep_L<48>(p, st); break;
-        case 64: e = launch_sweep_L<64>(p, st); break;
-        case 128: e = launch_sweep_L<128>(p, st); break;
-        case 256: e = launch_sweep_L<256>(p, st); break;
-        default:
-            hipLaunchKernelGGL(k_sweep_generic, dim3((p.s.P + 63) / 64), dim3(64), 0, st, p);
-            e = hipGetLastError();
-        }
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_advance_sweeps, dim3(1), dim3(1), 0, st, p.s.ctl, (uint32_t)M);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
+#define MC_FOR_EACH_SIZE(X) X(4) X(8) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(64) X(128) X(256)
+
+hipError_t prepare_sweeps(const SizeDev &s, const SizePlan &p) {
+    switch (s.L) {
+#define MC_CASE(LL) \
+    case LL: return prepare_L<LL>(p);
+        MC_FOR_EACH_SIZE(MC_CASE)
+#undef MC_CASE
+    default:
+        return hipSuccess;
     }
-    return hipSuccess;
+}
+
+hipError_t launch_sweeps(const SizeDev &s, const SizePlan &pl, int64_t M, void *trace, int32_t *hist,
+                         hipStream_t st) {
+    SweepParams p{};
+    p.s = s;
+    p.M = M;
+    p.trace = trace;
+    p.hist = hist;
+    p.cpb = pl.cpb;
+    p.lds_hist = 0;
+    if (pl.kind == kSweepGeneric) {
+        hipLaunchKernelGGL(k_sweep_generic, dim3((s.P + 63) / 64), dim3(64), 0, st, p);
+        return hipGetLastError();
+    }
+    switch (s.L) {
+#define MC_CASE(LL) \
+    case LL: return launch_L<LL>(p, pl, st);
+        MC_FOR_EACH_SIZE(MC_CASE)
+#undef MC_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Batched sweeps: every size of a context in one persistent launch.  Blocks
+// take tiles (a size and a run of its chains) from a queue ordered largest
+// lattice first and sweep them exactly as the single-size kernel does, so a
+// chain's trajectory does not depend on how it is batched (its random words
+// are keyed by its own size and index).
+// ---------------------------------------------------------------------------
+struct BatchParams {
+    SizeDev sizes[kMaxSizes];
+    void *trace[kMaxSizes];
+    int32_t *hist[kMaxSizes];
+    int32_t cpb[kMaxSizes];
+    int32_t kind[kMaxSizes];
+    const Tile *tiles;
+    int32_t n_tiles;
+    int32_t *counter;
+    int64_t M;
+};
+
+template <int L>
+__device__ __forceinline__ void batched_tile(const BatchParams &p, int si, int c0, uint32_t *smem) {
+    if (p.kind[si] == kSweepLdsTab)
+        sweep_tile_lds<L, true>(p.sizes[si], c0, p.cpb[si], p.M, p.trace[si], p.hist[si], true, smem);
+    else
+        sweep_tile_lds<L, false>(p.sizes[si], c0, p.cpb[si], p.M, p.trace[si], p.hist[si], true, smem);
+}
+
+__global__ __launch_bounds__(64) void k_sweep_batched(BatchParams p) {
+    extern __shared__ uint32_t smem[];
+    __shared__ int s_tile;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_tile = atomicAdd(p.counter, 1);
+        __syncthreads();
+        const int t = s_tile;
+        if (t >= p.n_tiles) break;  // every block leaves once the queue is empty
+        const Tile tl = p.tiles[t];
+        switch (p.sizes[tl.size].L) {
+#define MC_CASE(LL) \
+    case LL: batched_tile<LL>(p, tl.size, tl.c0, smem); break;
+            MC_CASE(4) MC_CASE(8) MC_CASE(12) MC_CASE(16) MC_CASE(20) MC_CASE(24) MC_CASE(32) MC_CASE(40) MC_CASE(48)
+            MC_CASE(64)
+#undef MC_CASE
+        default:
+            break;
+        }
+    }
+}
+
+__global__ void k_reset_counter(int32_t *c) { *c = 0; }
+
+hipError_t prepare_batched(size_t lds_bytes) {
+    static size_t allowed = 0;
+    if (lds_bytes > kLdsMax) return hipErrorInvalidValue;
+    return allow_lds((const void *)k_sweep_batched, allowed, lds_bytes);
+}
+
+hipError_t launch_sweeps_batched(const SizeDev *sizes, const SizePlan *plans, int n_sizes, const Tile *tiles_dev,
+                                 int n_tiles, int32_t *counter_dev, int grid, size_t lds_bytes, int64_t M,
+                                 void *const *trace, int32_t *const *hist, hipStream_t st) {
+    if (n_sizes > kMaxSizes) return hipErrorInvalidValue;
+    BatchParams p{};
+    for (int i = 0; i < n_sizes; ++i) {
+        p.sizes[i] = sizes[i];
+        p.trace[i] = trace[i];
+        p.hist[i] = hist[i];
+        p.cpb[i] = plans[i].cpb;
+        p.kind[i] = plans[i].kind;
+    }
+    p.tiles = tiles_dev;
+    p.n_tiles = n_tiles;
+    p.counter = counter_dev;
+    p.M = M;
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, counter_dev);
+    hipLaunchKernelGGL(k_sweep_batched, dim3(grid), dim3(64), lds_bytes, st, p);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
