@@ -188,6 +188,47 @@ mc_status mc_graph_create(mc_ctx *ctx, int64_t n_sweeps, int32_t n_iters, void *
 mc_status mc_graph_launch(mc_ctx *ctx, mc_graph *graph);
 mc_status mc_graph_destroy(mc_graph *graph);
 
+/* ------------------------------------------------------------------------
+   Learned initial weight.  A fully connected fp32 network with inputs
+   (1/L, e = E/N), two tanh layers of 64 units and a linear output f that
+   approximates the entropy per site ln g(E)/N.  A converged multicanonical
+   weight gives its training targets: a flat histogram means D(E) w(E) is
+   constant (Sec. 3.1), so ln g = -ln w + const, the constant fixed by
+   sum_E g(E) = 2^N.  For a new lattice size the network proposes
+   ln w = -N f, from which the recursion (eq. new_weight) continues; ln w = 0
+   (w^(1) = 1) remains the fallback.  These calls need no context: they take
+   device pointers and a HIP stream and return without waiting, except
+   mc_mlp_train with loss_host.
+   Parameters: mc_mlp_n_params() floats, laid out W1[64][2] | b1[64] |
+   W2[64][64] | b2[64] | W3[64] | b3.  Samples: x [n][2], targets t [n],
+   optional sample weights w [n] (NULL = 1).  Loss: sum w (y-t)^2 / sum w.
+   workspace: mc_mlp_workspace_bytes(n) bytes of device memory.
+   Errors: MC_EINVAL (NULL pointer, n < 1, bad L), MC_EHIP. */
+int32_t mc_mlp_n_params(void);
+size_t mc_mlp_workspace_bytes(int32_t n);
+/* Glorot-uniform weights (Philox words of domain 3, key (seed, 0)), zero biases. */
+mc_status mc_mlp_init(float *params_dev, uint32_t seed, void *hip_stream);
+/* y_dev [n] = f(x_dev). */
+mc_status mc_mlp_forward(const float *params_dev, const float *x_dev, int32_t n, float *y_dev, void *hip_stream);
+/* grad_dev [n_params] = d loss / d params; loss_dev (nullable) [1]. */
+mc_status mc_mlp_loss_grad(const float *params_dev, const float *x_dev, const float *t_dev, const float *w_dev,
+                           int32_t n, float *grad_dev, float *loss_dev, void *workspace_dev, void *hip_stream);
+/* `steps` full-batch Adam steps (beta 0.9/0.999, eps 1e-8) at rate lr.
+   adam_dev: 2 n_params floats of moment estimates (zeros at the start);
+   *step_io: steps taken so far (host, updated); loss_host (nullable): loss
+   before the last step (synchronises). */
+mc_status mc_mlp_train(float *params_dev, const float *x_dev, const float *t_dev, const float *w_dev, int32_t n,
+                       int32_t steps, float lr, float *adam_dev, int32_t *step_io, float *loss_host,
+                       void *workspace_dev, void *hip_stream);
+/* Training samples of one converged ln w (device, n_bins values): x_dev
+   [n_bins][2] = (1/L, e_b) with e_b the energy per site of the centre of bin
+   b, t_dev [n_bins] = (-ln w_b + c)/N. */
+mc_status mc_mlp_targets(const double *lnW_dev, int32_t L, int32_t bin_shift, float *x_dev, float *t_dev,
+                         void *hip_stream);
+/* Proposed ln w of a lattice size: lnW_dev [n_bins] = -N f(1/L, e_b). */
+mc_status mc_mlp_predict_weights(const float *params_dev, int32_t L, int32_t bin_shift, double *lnW_dev,
+                                 void *hip_stream);
+
 /* Wait for all work of the context. */
 mc_status mc_sync(mc_ctx *ctx);
 

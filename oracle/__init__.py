@@ -61,7 +61,7 @@ def lib():
 def _bind_mlp(L):
     L.orc_mlp_n_params.restype = _i32
     L.orc_mlp_forward.argtypes = [_p, _p, _i32, _p]
-    L.orc_mlp_loss_grad.argtypes = [_p, _p, _p, _i32, _p]
+    L.orc_mlp_loss_grad.argtypes = [_p, _p, _p, _p, _i32, _p]
     L.orc_mlp_loss_grad.restype = _dbl
 
 
@@ -94,6 +94,31 @@ def det_log(h):
 
 def threshold(d):
     return int(lib().orc_threshold(float(d)))
+
+
+def mlp_n_params():
+    return int(lib().orc_mlp_n_params())
+
+
+def mlp_forward(params, x):
+    """fp64 forward of the 2-64-64-1 tanh network; x: (n, 2)."""
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    xx = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 2)
+    y = np.zeros(len(xx))
+    lib().orc_mlp_forward(_ptr(p), _ptr(xx), len(xx), _ptr(y))
+    return y
+
+
+def mlp_loss_grad(params, x, t, w=None):
+    """Weighted mean squared error and its gradient (fp64)."""
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    xx = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 2)
+    tt = np.ascontiguousarray(t, dtype=np.float64)
+    ww = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+    g = np.zeros(mlp_n_params())
+    loss = lib().orc_mlp_loss_grad(_ptr(p), _ptr(xx), _ptr(tt), _ptr(ww) if ww is not None else None, len(xx),
+                                   _ptr(g))
+    return float(loss), g
 
 
 def n_bins(L, bin_shift):

@@ -23,7 +23,9 @@ _STATUS = {0: "MC_OK", -1: "MC_EINVAL", -2: "MC_ENOMEM", -3: "MC_ENODEV", -4: "M
 EXPORTED = ["mc_create", "mc_destroy", "mc_n_bins", "mc_trace_elem_bytes", "mc_lattice_words", "mc_init_weights",
             "mc_run_chains", "mc_join", "mc_update_weights", "mc_get_levels", "mc_get_lattice", "mc_get_counters",
             "mc_get_weights", "mc_get_progress", "mc_set_chains_per_block", "mc_get_launch", "mc_autotune",
-            "mc_graph_create", "mc_graph_launch", "mc_graph_destroy", "mc_sync", "mc_last_error"]
+            "mc_graph_create", "mc_graph_launch", "mc_graph_destroy", "mc_sync", "mc_last_error",
+            "mc_mlp_n_params", "mc_mlp_workspace_bytes", "mc_mlp_init", "mc_mlp_forward", "mc_mlp_loss_grad",
+            "mc_mlp_train", "mc_mlp_targets", "mc_mlp_predict_weights"]
 
 
 class MCError(RuntimeError):
@@ -74,8 +76,18 @@ def lib():
     L.mc_graph_destroy.argtypes = [p]
     L.mc_sync.argtypes = [p]
     L.mc_last_error.restype = ctypes.c_char_p
+    L.mc_mlp_n_params.restype = i32
+    L.mc_mlp_workspace_bytes.argtypes = [i32]
+    L.mc_mlp_workspace_bytes.restype = ctypes.c_size_t
+    L.mc_mlp_init.argtypes = [p, u32, p]
+    L.mc_mlp_forward.argtypes = [p, p, i32, p, p]
+    L.mc_mlp_loss_grad.argtypes = [p, p, p, p, i32, p, p, p, p]
+    L.mc_mlp_train.argtypes = [p, p, p, p, i32, i32, ctypes.c_float, p, ctypes.POINTER(i32), p, p, p]
+    L.mc_mlp_targets.argtypes = [p, i32, i32, p, p, p]
+    L.mc_mlp_predict_weights.argtypes = [p, i32, i32, p, p]
     for f in EXPORTED:
-        if f not in ("mc_n_bins", "mc_trace_elem_bytes", "mc_lattice_words", "mc_last_error"):
+        if f not in ("mc_n_bins", "mc_trace_elem_bytes", "mc_lattice_words", "mc_last_error", "mc_mlp_n_params",
+                     "mc_mlp_workspace_bytes"):
             getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -302,3 +314,100 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+# --------------------------------------------------------------------------- #
+# Learned initial weight (the 2-64-64-1 tanh network of mc.h)                 #
+# --------------------------------------------------------------------------- #
+def _stream_ptr(stream=None):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def mlp_n_params():
+    return int(lib().mc_mlp_n_params())
+
+
+class MLP:
+    """Parameters, Adam state and workspace of one network on the GPU."""
+
+    def __init__(self, seed=1, params=None, stream=None):
+        import torch
+
+        self.n_params = mlp_n_params()
+        self.stream = stream
+        if params is None:
+            self.params = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+            _check(lib().mc_mlp_init(_dev_ptr(self.params, torch.float32), int(seed), _stream_ptr(stream)))
+        else:
+            self.params = torch.as_tensor(params, dtype=torch.float32).cuda().contiguous()
+        self.adam = torch.zeros(2 * self.n_params, dtype=torch.float32, device="cuda")
+        self.step = ctypes.c_int32(0)
+        self._ws = None
+
+    def _workspace(self, n):
+        import torch
+
+        need = int(lib().mc_mlp_workspace_bytes(int(n)))
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+        return ctypes.c_void_p(self._ws.data_ptr())
+
+    def forward(self, x):
+        import torch
+
+        x = x.contiguous()
+        n = x.numel() // 2
+        y = torch.empty(n, dtype=torch.float32, device="cuda")
+        _check(lib().mc_mlp_forward(_dev_ptr(self.params, torch.float32), _dev_ptr(x, torch.float32), n,
+                                    _dev_ptr(y, torch.float32), _stream_ptr(self.stream)))
+        return y
+
+    def loss_grad(self, x, t, w=None):
+        import torch
+
+        n = t.numel()
+        g = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        _check(lib().mc_mlp_loss_grad(_dev_ptr(self.params, torch.float32), _dev_ptr(x, torch.float32),
+                                      _dev_ptr(t, torch.float32), _dev_ptr(w, torch.float32) if w is not None else None,
+                                      n, _dev_ptr(g, torch.float32), _dev_ptr(loss, torch.float32),
+                                      self._workspace(n), _stream_ptr(self.stream)))
+        return loss, g
+
+    def train(self, x, t, w=None, steps=1000, lr=1e-3):
+        """Full-batch Adam steps; returns the loss before the last step."""
+        import torch
+
+        n = t.numel()
+        loss = ctypes.c_float()
+        _check(lib().mc_mlp_train(_dev_ptr(self.params, torch.float32), _dev_ptr(x, torch.float32),
+                                  _dev_ptr(t, torch.float32), _dev_ptr(w, torch.float32) if w is not None else None,
+                                  n, int(steps), float(lr), _dev_ptr(self.adam, torch.float32), ctypes.byref(self.step),
+                                  ctypes.byref(loss), self._workspace(n), _stream_ptr(self.stream)))
+        return float(loss.value)
+
+    def predict_weights(self, L, bin_shift=1):
+        """Proposed ln w (numpy, fp64) of an L x L lattice."""
+        import torch
+
+        nb = ((L * L) >> bin_shift) + 1
+        w = torch.empty(nb, dtype=torch.float64, device="cuda")
+        _check(lib().mc_mlp_predict_weights(_dev_ptr(self.params, torch.float32), int(L), int(bin_shift),
+                                            _dev_ptr(w, torch.float64), _stream_ptr(self.stream)))
+        return w.cpu().numpy()
+
+
+def mlp_targets(lnW, L, bin_shift=1, stream=None):
+    """Training samples (x [n][2], t [n]) of a converged ln w, built on the GPU."""
+    import torch
+
+    w = torch.as_tensor(np.asarray(lnW, dtype=np.float64)).cuda().contiguous()
+    nb = w.numel()
+    x = torch.empty((nb, 2), dtype=torch.float32, device="cuda")
+    t = torch.empty(nb, dtype=torch.float32, device="cuda")
+    _check(lib().mc_mlp_targets(_dev_ptr(w, torch.float64), int(L), int(bin_shift), _dev_ptr(x, torch.float32),
+                                _dev_ptr(t, torch.float32), _stream_ptr(stream)))
+    return x, t

@@ -168,6 +168,8 @@ hipError_t enqueue_sweeps(mc_ctx *ctx, hipStream_t st, int64_t M, void *const *t
 
 }  // namespace
 
+void mcgpu::set_last_error(const char *msg) { g_err = msg; }
+
 extern "C" {
 
 const char *mc_last_error(void) { return g_err.c_str(); }

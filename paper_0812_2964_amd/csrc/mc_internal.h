@@ -72,4 +72,7 @@ hipError_t launch_join(const SizeDev &s, const void *trace, int64_t M, int32_t *
                        hipStream_t st);
 hipError_t launch_update(const SizeDev &s, int32_t *hist, hipStream_t st);
 
+// Message returned by mc_last_error() on this thread (mc_api.hip).
+void set_last_error(const char *msg);
+
 }  // namespace mcgpu
