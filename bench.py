@@ -1,17 +1,24 @@
 """Benchmark: parallel multicanonical Metropolis chains on the 2D Ising model
-(arXiv 0812.2964, Algorithm steps 2-5 and eq. new_weight) on one MI355X.
+(arXiv 0812.2964: Algorithm steps 2-5 and eq. new_weight) on one MI355X.
 
-Workload (default): L = 32, 4096 chains x 10^5 sweeps per step, width-8 energy
-bins (513), the prior ln w of tests/golden/lnW_L32_prior.npy, seed 1.
-One step = mc_run_chains (10^5 sweeps of every chain) + mc_join (detailed-balance
-joints over all 4096 chains) + mc_update_weights (eq. new_weight + flatness +
-re-tabulation).  Inputs are resident in device memory before timing starts.
+Default workload (the one the headline metric is quoted on): L = 32, 4096
+chains x 10^5 sweeps per step, width-8 energy bins (513), the prior ln w of
+tests/golden/lnW_L32_prior.npy, seed 1.  One step = mc_run_chains (10^5 sweeps
+of every chain) + mc_join (detailed-balance joints over all 4096 chains) +
+mc_update_weights (eq. new_weight, flatness, re-tabulation).  Inputs are
+resident in device memory before the timed region.
 
-Prints one JSON line (rank 0) with the throughput in spin-flip attempts/s, the
-sweep kernel's position against the integer-ALU roofline, and the CPU oracle
-timed on a bounded sample of the same workload.
+Prints one JSON line with the throughput in spin-flip attempts/s, the sweep
+kernel against the integer-ALU roofline, and the CPU oracle timed on a
+bounded sample of the same workload.
+
+Other workloads (--workload): recursion8 (L = 8, 16 chains, 10^4 sweeps, ten
+iterations from ln w = 0), batched (L = 16, 24, 32, 48, 64, 2048 chains each,
+graph-captured iterations), l128 (L = 128, 8192 chains), and copy (a plain
+device copy of known size, to calibrate the HBM byte counters).
 """
 import argparse
+import hashlib
 import json
 import os
 import re
@@ -29,6 +36,7 @@ sys.path.insert(0, ROOT)
 OPS_PER_ATTEMPT = 31
 # MI355X: 256 CUs x 64 lanes x 2.4 GHz of full-rate 32-bit vector ALU operations.
 ALU_PEAK_OPS = 256 * 64 * 2.4e9
+METRIC = "spin-flip attempts/s (multicanonical Ising, 1 GPU); iterations to flat H"
 
 
 def log(msg):
@@ -40,22 +48,26 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--L", type=int, default=32)
-    ap.add_argument("--chains", type=int, default=4096)
-    ap.add_argument("--sweeps", type=int, default=100000)
+    ap.add_argument("--workload", default="l32", choices=["l32", "recursion8", "batched", "l128", "copy"])
+    ap.add_argument("--chains", type=int, default=None)
+    ap.add_argument("--sweeps", type=int, default=None)
+    ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--cpu-chains", type=int, default=64)
     ap.add_argument("--cpu-sweeps", type=int, default=4000)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     return ap.parse_args()
+
+
+def kernel_source_hash():
+    src = os.path.join(ROOT, "paper_0812_2964_amd", "csrc", "mc_kernels.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()
 
 
 def traffic_from_profiles(L, P, M):
     """HBM bytes per sweep launch from the committed counter summary, if it was
-    taken on the current kernel source; else None."""
-    import hashlib
-
-    path = os.path.join(ROOT, "profiles", "sweep_L32_4096x1e5_counters.md")
-    src = os.path.join(ROOT, "paper_0812_2964_amd", "csrc", "mc_kernels.hip")
+    taken on the current kernel source and workload; else None."""
+    path = os.path.join(ROOT, "profiles", "k_sweep_lds_L32_4096x1e5_counters.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -64,7 +76,7 @@ def traffic_from_profiles(L, P, M):
     m_cfg = re.search(r"workload:\s*L=(\d+) chains=(\d+) sweeps=(\d+)", txt)
     if not (m_hash and m_bytes and m_cfg):
         return None
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != m_hash.group(1):
+    if kernel_source_hash() != m_hash.group(1):
         return None
     if (int(m_cfg.group(1)), int(m_cfg.group(2)), int(m_cfg.group(3))) != (L, P, M):
         return None
@@ -84,28 +96,30 @@ def cpu_baseline(L, lnW, chains, sweeps):
                       % (chains, sweeps, L, att, dt)}
 
 
-def main():
-    a = parse()
-    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the method's chains live on a single device here "
-              "(multi-GPU sharding is a design note, not built); use --gpus 1", file=sys.stderr)
-        sys.exit(2)
-    import torch
+def base_record(a, value, ms_per_step, config, dtype="u32"):
+    return {"metric": METRIC, "value": value, "unit": "spin-flip attempts/s", "n_gpus": 1, "steps": a.steps,
+            "warmup": a.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
 
-    import paper_0812_2964_amd as mc
 
-    torch.cuda.set_device(0)
-    L, P, M = a.L, a.chains, a.sweeps
+def roofline(attempts, kernel_s, traffic):
+    achieved = attempts * OPS_PER_ATTEMPT / kernel_s
+    return {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_OPS / 1e12, "unit": "Tops/s",
+            "frac": achieved / ALU_PEAK_OPS, "traffic": traffic, "ops_per_attempt": OPS_PER_ATTEMPT,
+            "kernel_ms": kernel_s * 1e3}
+
+
+def bench_l32(a, torch, mc):
+    L = 32
+    P = a.chains or 4096
+    M = a.sweeps or 100000
     N = L * L
-    lnW = np.load(os.path.join(ROOT, "tests", "golden", "lnW_L32_prior.npy")) if L == 32 else None
+    lnW = np.load(os.path.join(ROOT, "tests", "golden", "lnW_L32_prior.npy"))
     stream = torch.cuda.current_stream()
     ctx = mc.Context([(L, P, 1, 1)], stream=stream)
     ctx.init_weights(lnW)
-    trace = ctx.new_trace(M)
-    hist = ctx.new_hist()
-    cut = ctx.new_cut()
+    trace, hist, cut = ctx.new_trace(M), ctx.new_hist(), ctx.new_cut()
     log("bench: L=%d chains=%d sweeps=%d, warmup %d, steps %d" % (L, P, M, a.warmup, a.steps))
-
     ev = []
 
     def step(timed):
@@ -131,38 +145,141 @@ def main():
         log("bench: step %d done (%.2f s so far)" % (s + 1, time.perf_counter() - t0))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    sweep_ms = [e0.elapsed_time(e1) for e0, e1 in ev]
-    attempts_step = P * M * N
-    value = a.steps * attempts_step / elapsed
-    avg_sweep_s = sum(sweep_ms) / len(sweep_ms) / 1e3
-    achieved = attempts_step * OPS_PER_ATTEMPT / avg_sweep_s
-    seam, rnd, sweep_idx = ctx.counters()
-    res = {
-        "metric": "spin-flip attempts/s (multicanonical Ising, 1 GPU); iterations to flat H",
-        "value": value,
-        "unit": "spin-flip attempts/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": elapsed / a.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u32",
-        "data": "synthetic",
-        "config": {"workload": "2D Ising L=%d periodic, %d chains x %d sweeps per step (run + joint + weight "
-                               "update), width-8 energy bins, prior ln w fixture, seed 1" % (L, P, M),
-                   "L": L, "chains": P, "sweeps_per_step": M, "bins": ctx.n_bins(), "parallelism": "chains"},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_OPS / 1e12, "unit": "Tops/s",
-                     "frac": achieved / ALU_PEAK_OPS, "traffic": traffic_from_profiles(L, P, M),
-                     "kernel": "k_sweep (mc_run_chains)", "kernel_ms": avg_sweep_s * 1e3,
-                     "ops_per_attempt": OPS_PER_ATTEMPT},
-        "sweep_attempts_per_s": attempts_step / avg_sweep_s,
-    }
+    sweep_s = sum(e0.elapsed_time(e1) for e0, e1 in ev) / len(ev) / 1e3
+    att = P * M * N
+    cpb, kind, _ = ctx.launch()
+    res = base_record(a, a.steps * att / elapsed, elapsed / a.steps * 1e3,
+                      {"workload": "2D Ising L=%d periodic, %d chains x %d sweeps per step (run + joint + weight "
+                                   "update), width-8 energy bins, prior ln w fixture, seed 1" % (L, P, M),
+                       "L": L, "chains": P, "sweeps_per_step": M, "bins": ctx.n_bins(), "parallelism": "chains",
+                       "chains_per_block": cpb, "kernel_kind": kind})
+    res["roofline"] = roofline(att, sweep_s, traffic_from_profiles(L, P, M))
+    res["roofline"]["kernel"] = "k_sweep_lds<32,true> (mc_run_chains)"
+    res["sweep_attempts_per_s"] = att / sweep_s
     ctx.close()
     if not a.no_cpu:
         log("bench: timing the CPU oracle on a sample")
         res["cpu_baseline"] = cpu_baseline(L, lnW, a.cpu_chains, a.cpu_sweeps)
+    return res
+
+
+def bench_recursion8(a, torch, mc):
+    """L = 8, 16 chains, 10^4 sweeps, ten iterations of the recursion from ln w = 0."""
+    L, P = 8, a.chains or 16
+    M = a.sweeps or 10000
+    iters = a.iters or 10
+    ctx = mc.Context([(L, P, 1, 1)])
+    trace, hist, cut = ctx.new_trace(M), ctx.new_hist(), ctx.new_cut()
+    g = ctx.graph(M, iters, [trace], [hist], [cut])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.launch()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    upd, first_flat, last_flat, _ = ctx.progress()
+    g.close()
+    ctx.close()
+    res = base_record(a, iters * P * M * L * L / dt, dt * 1e3,
+                      {"workload": "2D Ising L=8, 16 chains x 10^4 sweeps, 10 graph-captured iterations from ln w = 0"
+                                   ", 33 bins, seed 1", "L": L, "chains": P, "sweeps_per_iter": M, "iterations": iters})
+    res["iterations_to_flat"] = first_flat or None
+    return res
+
+
+def bench_batched(a, torch, mc):
+    Ls = [16, 24, 32, 48, 64]
+    P = a.chains or 2048
+    M = a.sweeps or 100000
+    iters = a.iters or 20
+    sizes = [(L, P, 1, 1) for L in Ls]
+    ctx = mc.Context(sizes)
+    log("bench batched: autotuning")
+    cpbs = ctx.autotune(50)
+    trs = [ctx.new_trace(M, i) for i in range(len(Ls))]
+    hs = [ctx.new_hist(i) for i in range(len(Ls))]
+    cuts = [ctx.new_cut(i) for i in range(len(Ls))]
+    g = ctx.graph(M, 1, trs, hs, cuts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(iters):
+        g.launch()
+        torch.cuda.synchronize()
+        log("bench batched: iteration %d done (%.1f s)" % (it + 1, time.perf_counter() - t0))
+    dt = time.perf_counter() - t0
+    flats = {L: ctx.progress(i)[1] or None for i, L in enumerate(Ls)}
+    att = iters * P * M * sum(L * L for L in Ls)
+    g.close()
+    ctx.close()
+    res = base_record(a, att / dt, dt / iters * 1e3,
+                      {"workload": "batched L in {16,24,32,48,64}, %d chains each x %d sweeps, %d graph-captured "
+                                   "iterations from ln w = 0, one persistent launch" % (P, M, iters),
+                       "L": Ls, "chains_per_L": P, "sweeps_per_iter": M, "iterations": iters,
+                       "chains_per_block": cpbs})
+    res["iterations_to_flat"] = flats
+    return res
+
+
+def bench_l128(a, torch, mc):
+    L, P = 128, a.chains or 8192
+    M = a.sweeps or 1000
+    ctx = mc.Context([(L, P, 1, 1)])
+    trace, hist, cut = ctx.new_trace(M), ctx.new_hist(), ctx.new_cut()
+    stream = torch.cuda.current_stream()
+    times = []
+    for s in range(a.warmup + a.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ctx.run_chains(M, trace, hist)
+        e1.record(stream)
+        ctx.join(trace, cut, hist)
+        ctx.update_weights(hist, want=False)
+        torch.cuda.synchronize()
+        if s >= a.warmup:
+            times.append(e0.elapsed_time(e1) / 1e3)
+        log("bench l128: step %d done" % (s + 1))
+    att = P * M * L * L
+    sweep_s = sum(times) / len(times)
+    cpb, kind, _ = ctx.launch()
+    ctx.close()
+    res = base_record(a, att / sweep_s, sweep_s * 1e3,
+                      {"workload": "2D Ising L=128, %d chains x %d sweeps per step, ln w = 0 start" % (P, M),
+                       "L": L, "chains": P, "sweeps_per_step": M, "kernel_kind": kind})
+    res["roofline"] = roofline(att, sweep_s, None)
+    return res
+
+
+def bench_copy(a, torch):
+    """A plain device-to-device copy of known size (counter calibration)."""
+    n = a.copy_bytes // 4
+    src = torch.ones(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return {"copy_bytes": n * 4, "copies": 3}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the chains of one ensemble live on a single device here "
+              "(sharding across GPUs is a design note, not built); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_0812_2964_amd as mc
+
+    torch.cuda.set_device(0)
+    if a.workload == "copy":
+        res = bench_copy(a, torch)
+    elif a.workload == "recursion8":
+        res = bench_recursion8(a, torch, mc)
+    elif a.workload == "batched":
+        res = bench_batched(a, torch, mc)
+    elif a.workload == "l128":
+        res = bench_l128(a, torch, mc)
+    else:
+        res = bench_l32(a, torch, mc)
     print(json.dumps(res), flush=True)
 
 
