@@ -99,8 +99,8 @@ int32_t mc_lattice_words(const mc_ctx *ctx, int32_t size_idx);
 mc_status mc_init_weights(mc_ctx *ctx, int32_t size_idx, const double *lnW_host, int32_t n_bins);
 
 /* Algorithm step 2 for every size of the context, in one launch: each chain
-   makes n_sweeps sweeps from where it stopped (chains are independent from
-   first to last, Sec. 2 remarks).  For size s:
+   makes n_sweeps sweeps from where it stopped (each chain is generated
+   independently over the whole run, Sec. 2).  For size s:
      trace_dev[s]: device, [n_chains][n_sweeps] of E/4 after each sweep;
      hist_dev[s]:  device int32 [n_bins]; the bin of every configuration of
                    every chain is added to it (so it must hold zeros, or the

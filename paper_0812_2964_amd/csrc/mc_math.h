@@ -1,8 +1,8 @@
 // mc_math.h -- arithmetic shared by the kernels of the library (device code).
 //
-//  * Philox4x32-10 (Salmon, Moraes, Dror and Shaw, "Parallel random numbers:
-//    as easy as 1, 2, 3", SC'11): ten rounds of two 32x32->64 products and
-//    xors, key bumped by the golden-ratio / sqrt(3)-1 Weyl constants.
+//  * Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11): ten rounds of two
+//    32x32->64 products and xors, key bumped by the golden-ratio and
+//    sqrt(3)-1 Weyl constants.
 //  * exp(d) for d in [-23, 0] and ln(h) for integers h >= 1 by a fixed sequence
 //    of binary64 operations (Cody-Waite reduction + Taylor series; the atanh
 //    series of ln((1+s)/(1-s))), so that thresholds and weights come out the
