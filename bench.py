@@ -60,14 +60,17 @@ def parse():
 
 
 def kernel_source_hash():
-    src = os.path.join(ROOT, "paper_0812_2964_amd", "csrc", "mc_kernels.hip")
-    return hashlib.sha256(open(src, "rb").read()).hexdigest()
+    """sha256 over the sources the sweep kernel is compiled from."""
+    h = hashlib.sha256()
+    for f in ("mc_kernels.hip", "mc_math.h", "mc_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_0812_2964_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
 
 
 def traffic_from_profiles(L, P, M):
     """HBM bytes per sweep launch from the committed counter summary, if it was
     taken on the current kernel source and workload; else None."""
-    path = os.path.join(ROOT, "profiles", "k_sweep_lds_L32_4096x1e5_counters.md")
+    path = os.path.join(ROOT, "profiles", "k_sweep_L32_4096x1e5_counters.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -154,7 +157,8 @@ def bench_l32(a, torch, mc):
                        "L": L, "chains": P, "sweeps_per_step": M, "bins": ctx.n_bins(), "parallelism": "chains",
                        "chains_per_block": cpb, "kernel_kind": kind})
     res["roofline"] = roofline(att, sweep_s, traffic_from_profiles(L, P, M))
-    res["roofline"]["kernel"] = "k_sweep_lds<32,true> (mc_run_chains)"
+    res["roofline"]["kernel"] = {0: "k_sweep_lds<32,true>", 1: "k_sweep_lds<32,false>", 2: "k_sweep_glb<32>",
+                                 3: "k_sweep_generic", 4: "k_sweep_pc<32>"}[kind] + " (mc_run_chains)"
     res["sweep_attempts_per_s"] = att / sweep_s
     ctx.close()
     if not a.no_cpu:

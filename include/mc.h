@@ -161,12 +161,14 @@ mc_status mc_get_progress(mc_ctx *ctx, int32_t size_idx, int32_t *updates, int32
    mc_set_chains_per_block: chains per 64-lane workgroup (1..64) of one size.
    mc_get_launch: chains per workgroup, kernel kind (0 lattice and thresholds
    in LDS, 1 lattice in LDS, 2 lattice streamed from global memory, 3 generic
-   bit-by-bit kernel for L not among the compiled sizes) and whether the sizes
-   run batched in one persistent launch (all sizes keep lattices in LDS).
+   bit-by-bit kernel for L not among the compiled sizes, 4 as 0 with the random
+   words made by a second wave of the workgroup) and whether the sizes run
+   batched in one persistent launch (all sizes keep lattices in LDS).
+   mc_set_chains_per_block prefers kind 4 where it fits.
    mc_autotune: times probe_sweeps sweeps of every size on copies of the chain
-   state for 16, 32 and 64 chains per workgroup and keeps the fastest
-   (chains_per_block_out: n_sizes values, nullable).  The chains are not
-   advanced.  Both setters fail with MC_ESTATE while graphs of the context
+   state for 16, 32 and 64 chains per workgroup, with and without the producer
+   wave, and keeps the fastest (chains_per_block_out: n_sizes values,
+   nullable).  The chains are not advanced.  Both setters fail with MC_ESTATE while graphs of the context
    exist. */
 mc_status mc_set_chains_per_block(mc_ctx *ctx, int32_t size_idx, int32_t chains_per_block);
 mc_status mc_get_launch(mc_ctx *ctx, int32_t size_idx, int32_t *chains_per_block, int32_t *kind, int32_t *batched);

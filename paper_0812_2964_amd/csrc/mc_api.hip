@@ -97,11 +97,17 @@ void free_size(SizeDev &d) {
     d = SizeDev{};
 }
 
-// Default chains per block: as many as fit with the thresholds in LDS.
+// Default launch: the producer/consumer kernel with as many chains per
+// workgroup as fit in LDS, else the single-wave kernel with the thresholds in
+// LDS, else whatever fits.
 SizePlan default_plan(const SizeDev &d) {
-    SizePlan p = plan_sweeps(d, 64);
+    for (int cpb = 64; cpb >= 8; cpb /= 2) {
+        SizePlan q = plan_sweeps(d, cpb, true);
+        if (q.kind == kSweepPC) return q;
+    }
+    SizePlan p = plan_sweeps(d, 64, false);
     for (int cpb = 32; p.kind == kSweepLds && cpb >= 16; cpb /= 2) {
-        SizePlan q = plan_sweeps(d, cpb);
+        SizePlan q = plan_sweeps(d, cpb, false);
         if (q.kind == kSweepLdsTab) p = q;
     }
     return p;
@@ -451,7 +457,7 @@ mc_status mc_autotune(mc_ctx *ctx, int64_t probe_sweeps, int32_t *chains_per_blo
     hipEvent_t e0, e1;
     HIP_OR_FAIL(ctx, hipEventCreate(&e0));
     HIP_OR_FAIL(ctx, hipEventCreate(&e1));
-    const int cands[3] = {16, 32, 64};
+    const int cands[6] = {16, 32, 64, 16, 32, 64};  // producer/consumer kernel first, then single-wave
     hipError_t e = hipSuccess;
     for (size_t i = 0; i < ctx->sizes.size() && e == hipSuccess; ++i) {
         HostSize &h = ctx->sizes[i];
@@ -471,8 +477,8 @@ mc_status mc_autotune(mc_ctx *ctx, int64_t probe_sweeps, int32_t *chains_per_blo
         if (e == hipSuccess) e = hipMalloc((void **)&hs, (size_t)d.n_bins * 4);
         float best = 1e30f;
         SizePlan best_plan = h.plan;
-        for (int k = 0; k < 3 && e == hipSuccess; ++k) {
-            const SizePlan cand = plan_sweeps(d, cands[k]);
+        for (int k = 0; k < 6 && e == hipSuccess; ++k) {
+            const SizePlan cand = plan_sweeps(d, cands[k], k < 3);
             if (cand.kind == kSweepGeneric) break;
             e = prepare_sweeps(d, cand);
             float t_min = 1e30f;

@@ -39,11 +39,13 @@ enum SweepKind : int32_t {
     kSweepLds = 1,      // lattice in LDS, thresholds read from global memory
     kSweepGlobal = 2,   // lattice rows streamed from global memory (large L)
     kSweepGeneric = 3,  // any even L, bit by bit (L not among the compiled sizes)
+    kSweepPC = 4,       // lattice and thresholds in LDS, random words from a producer wave
 };
 
 struct SizePlan {
     int32_t cpb;        // chains per 64-lane block
     int32_t kind;       // SweepKind
+    int32_t R;          // rows per chunk of random words (kSweepPC)
     size_t lds_bytes;   // dynamic LDS per block
 };
 
@@ -57,7 +59,7 @@ struct Tile {
 
 // Kernel launchers (mc_kernels.hip).  All enqueue on `st` and return the
 // launch status.
-SizePlan plan_sweeps(const SizeDev &s, int chains_per_block);
+SizePlan plan_sweeps(const SizeDev &s, int chains_per_block, bool allow_pc = true);
 bool batchable(const SizePlan &p);
 hipError_t prepare_sweeps(const SizeDev &s, const SizePlan &p);  // kernel attributes; call outside capture
 hipError_t prepare_batched(size_t lds_bytes);

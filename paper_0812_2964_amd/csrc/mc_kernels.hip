@@ -258,6 +258,224 @@ __global__ __launch_bounds__(64) void k_sweep_lds(SweepParams p) {
     sweep_tile_lds<L, TAB_LDS>(p.s, blockIdx.x * p.cpb, p.cpb, p.M, p.trace, p.hist, p.lds_hist != 0, smem);
 }
 
+// ---------------------------------------------------------------------------
+// Producer/consumer sweeps (L <= 64).  A chain's attempts are strictly serial,
+// so a chain advances at most one instruction of its wave per issue slot; the
+// random words, which do not depend on the chain, are therefore generated by
+// a second wave of the workgroup (on another SIMD) into an LDS double buffer,
+// R rows of every chain at a time, while the first wave consumes the previous
+// R rows.  The two waves meet at one barrier per chunk.
+//
+// LDS layout (bytes, 16-aligned parts):
+//   [L*W*cpb u32]            lattice words, word (row*W + w) of chain l at (row*W+w)*cpb + l
+//   [(N+1)*8 u32]            thresholds
+//   [n_bins i32]             histogram
+//   [2][R][L/4][cpb] uint4   random words, group q of row r of chain l
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
+
+struct PcLayout {
+    size_t lat, tab, hist, ubuf, total;
+};
+
+__host__ __device__ inline PcLayout pc_layout(int L, int W, int N, int n_bins, int cpb, int R) {
+    PcLayout o;
+    o.lat = 0;
+    o.tab = align16((size_t)L * W * cpb * 4);
+    o.hist = o.tab + align16((size_t)(N + 1) * 8 * 4);
+    o.ubuf = o.hist + align16((size_t)n_bins * 4);
+    o.total = o.ubuf + (size_t)2 * R * (L / 4) * cpb * 16;
+    return o;
+}
+
+// a * b + c on 24-bit signed factors in one instruction (the backend would
+// otherwise emit a shift and a subtract).  Pure ALU.
+__device__ __forceinline__ uint32_t mad_i24(uint32_t a, int32_t b, uint32_t c) {
+    uint32_t r;
+    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
+    return r;
+}
+
+typedef __attribute__((address_space(3))) const uint32_t lds_u32;
+
+// Read a 32-bit word at a byte address of LDS.
+__device__ __forceinline__ uint32_t lds_load(uint32_t addr) { return *(lds_u32 *)(size_t)addr; }
+
+// One row of the consumer.  `lds` is the LDS base; mib is the byte address in
+// LDS of entry (m, 4) of the threshold table, i.e. tab + 4 (8m + 4), so the
+// threshold of a flip with `anti` anti-aligned neighbours is at mib - 4 anti and
+// an accepted flip moves mib by 4 (16 - 8 anti).  P0, P1 hold per site the
+// two bits of xu + xd + (right bond), all at row start.
+template <int L>
+__device__ __forceinline__ void pc_row(Row<L> &cur, const Row<L> &up, const Row<L> &dn, uint32_t &mib,
+                                       const char *lds, const uint4 *urow, int cpb) {
+    constexpr int W = (L + 31) / 32;
+    Row<L> xu, xd, hb, P0, P1;
+    const Row<L> nx = ring_next<L>(cur);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        xu.w[w] = cur.w[w] ^ up.w[w];
+        xd.w[w] = cur.w[w] ^ dn.w[w];
+        hb.w[w] = cur.w[w] ^ nx.w[w];
+        P0.w[w] = __builtin_amdgcn_bitop3_b32(xu.w[w], xd.w[w], hb.w[w], 0x96);  // parity
+        P1.w[w] = __builtin_amdgcn_bitop3_b32(xu.w[w], xd.w[w], hb.w[w], 0xE8);  // majority
+    }
+    int anti = (int)(bit_at<L>(xu, 0) + bit_at<L>(xd, 0) + bit_at<L>(hb, 0) + bit_at<L>(hb, L - 1));
+    uint32_t t = lds_load(mad_i24((uint32_t)anti, -4, mib));
+    uint32_t mibD = mib + mad_i24((uint32_t)anti, -32, 64u);
+    uint32_t f0 = 0;
+    uint4 u4 = urow[0], unext = u4;
+#pragma unroll
+    for (int x = 0; x < L; ++x) {
+        if ((x & 3) == 0) {
+            u4 = unext;
+            if (x + 4 < L) unext = urow[((x >> 2) + 1) * cpb];
+        }
+        const uint32_t u = (x & 3) == 0 ? u4.x : (x & 3) == 1 ? u4.y : (x & 3) == 2 ? u4.z : u4.w;
+        uint32_t an0 = 0, an1 = 0;
+        uint32_t t0n = 0, t1n = 0;
+        if (x + 1 < L) {
+            const int xn = x + 1;
+            const uint32_t h = bit_at<L>(hb, x);  // bond (x, x+1) at row start
+            uint32_t q;
+            if (xn == L - 1)  // its right neighbour is site 0, decided at the start of the row
+                q = bit_at<L>(xu, xn) + bit_at<L>(xd, xn) + (bit_at<L>(hb, xn) ^ f0);
+            else
+                q = bit_at<L>(P0, xn) + 2 * bit_at<L>(P1, xn);
+            an0 = q + h;
+            an1 = q + (h ^ 1u);
+            t0n = lds_load(mad_i24(an0, -4, mib));
+            t1n = lds_load(mad_i24(an1, -4, mibD));
+        }
+        const bool acc = u <= t;
+        if (x == 0) f0 = acc ? 1u : 0u;
+        cur.w[x >> 5] ^= (acc ? 1u : 0u) << (x & 31);
+        mib = acc ? mibD : mib;
+        if (x + 1 < L) {
+            anti = (int)(acc ? an1 : an0);
+            t = acc ? t1n : t0n;
+            mibD = mib + mad_i24((uint32_t)anti, -32, 64u);
+        }
+    }
+}
+
+// Random words of one chunk: rows y0 .. y0+R-1 of sweep g for every chain of
+// the block.  Producer thread `pt` of `np` threads.
+template <int L>
+__device__ __forceinline__ void pc_produce(uint4 *ub, int R, uint32_t y0, uint32_t g, int c0, int cpb, int P,
+                                           uint32_t k0, uint32_t k1, int pt, int np) {
+    constexpr int NQ = L / 4;
+    const int items = R * NQ * cpb;
+    for (int it = pt; it < items; it += np) {
+        const int l = it % cpb;
+        const int rq = it / cpb;  // r * NQ + q
+        const uint32_t c = (uint32_t)(c0 + l);
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if ((int)c < P) v = philox10(make_uint4(y0 * (uint32_t)NQ + (uint32_t)rq, g, c, kDomSweep), k0, k1);
+        ub[it] = v;
+    }
+}
+
+struct PcParams {
+    SizeDev s;
+    int64_t M;
+    void *trace;
+    int32_t *hist;
+    int32_t cpb;
+    int32_t R;
+};
+
+// Sweeps of chains c0 .. c0+cpb-1; wave 0 consumes, waves 1.. produce.
+template <int L>
+__device__ __forceinline__ void sweep_tile_pc(const SizeDev &s, int c0, int cpb, int R, int64_t M, void *trace,
+                                              int32_t *hist, uint32_t *smem) {
+    constexpr int W = (L + 31) / 32;
+    constexpr int N = L * L;
+    const PcLayout lay = pc_layout(L, W, N, s.n_bins, cpb, R);
+    char *lds = (char *)smem;
+    uint32_t *slat = (uint32_t *)(lds + lay.lat);
+    uint32_t *stab = (uint32_t *)(lds + lay.tab);
+    int32_t *shist = (int32_t *)(lds + lay.hist);
+    uint4 *ubuf = (uint4 *)(lds + lay.ubuf);
+    const int chunk_words = R * (L / 4) * cpb;  // uint4 per buffer
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int c = c0 + lane;
+    const bool consumer = wave == 0;
+    const bool active = consumer && lane < cpb && c < s.P;
+    const uint32_t k0 = s.seed, k1 = (uint32_t)L;
+    const uint32_t g0 = s.ctl->g;
+    for (int i = threadIdx.x; i < (N + 1) * 8; i += blockDim.x) stab[i] = s.tab[i];
+    for (int i = threadIdx.x; i < s.n_bins; i += blockDim.x) shist[i] = 0;
+    if (active)
+        for (int w = 0; w < L * W; ++w) slat[w * cpb + lane] = s.lat[(size_t)w * s.P + c];
+    const int np = blockDim.x - 64, pt = threadIdx.x - 64;
+    const int per_sweep = L / R;
+    const int64_t n_chunks = M * per_sweep;
+    if (!consumer) pc_produce<L>(ubuf, R, 0u, g0, c0, cpb, s.P, k0, k1, pt, np);
+    __syncthreads();
+
+    uint32_t mib = 0;
+    Row<L> up, cur, dn;
+    // absolute LDS byte address (dynamic LDS starts at address 0 of the workgroup's LDS)
+    const uint32_t tab_addr = (uint32_t)(size_t)(lds_u32 *)(stab);
+    if (active) mib = tab_addr + 4u * (8u * (uint32_t)s.lev[c] + 4u);
+    for (int64_t i = 0; i < n_chunks; ++i) {
+        const int64_t k = i / per_sweep;
+        const int y0 = (int)(i - k * per_sweep) * R;
+        if (active) {
+            const uint4 *ub = ubuf + (size_t)(i & 1) * chunk_words;
+            auto load = [&](int y) {
+                Row<L> r;
+#pragma unroll
+                for (int w = 0; w < W; ++w) r.w[w] = slat[(y * W + w) * cpb + lane];
+                return r;
+            };
+            if (y0 == 0) {
+                up = load(L - 1);
+                cur = load(0);
+                dn = load(1);
+            }
+            for (int r = 0; r < R; ++r) {
+                const int y = y0 + r;
+                pc_row<L>(cur, up, dn, mib, lds, ub + (size_t)r * (L / 4) * cpb + lane, cpb);
+#pragma unroll
+                for (int w = 0; w < W; ++w) slat[(y * W + w) * cpb + lane] = cur.w[w];
+                up = cur;
+                cur = dn;
+                dn = load(y + 2 < L ? y + 2 : y + 2 - L);
+            }
+            if (y0 + R == L) {
+                const int m = (int)((mib - tab_addr - 16u) >> 5);
+                const int ev = m - N / 2;
+                if (s.trace_bytes == 2)
+                    ((int16_t *)trace)[(size_t)c * M + k] = (int16_t)ev;
+                else
+                    ((int32_t *)trace)[(size_t)c * M + k] = ev;
+                atomicAdd(&shist[m >> s.bin_shift], 1);
+            }
+        } else if (!consumer && i + 1 < n_chunks) {
+            const int64_t k1s = (i + 1) / per_sweep;
+            const int y1 = (int)(i + 1 - k1s * per_sweep) * R;
+            pc_produce<L>(ubuf + (size_t)((i + 1) & 1) * chunk_words, R, (uint32_t)y1, g0 + (uint32_t)k1s, c0, cpb,
+                          s.P, k0, k1, pt, np);
+        }
+        __syncthreads();
+    }
+    if (active) {
+        s.lev[c] = (int)((mib - tab_addr - 16u) >> 5);
+        for (int w = 0; w < L * W; ++w) s.lat[(size_t)w * s.P + c] = slat[w * cpb + lane];
+    }
+    for (int i = threadIdx.x; i < s.n_bins; i += blockDim.x)
+        if (shist[i]) atomicAdd(&hist[i], shist[i]);
+    __syncthreads();
+}
+
+template <int L>
+__global__ __launch_bounds__(128) void k_sweep_pc(PcParams p) {
+    extern __shared__ uint32_t smem[];
+    sweep_tile_pc<L>(p.s, blockIdx.x * p.cpb, p.cpb, p.R, p.M, p.trace, p.hist, smem);
+}
+
 // Lattice rows streamed from global memory (large L); thresholds from global.
 template <int L>
 __global__ __launch_bounds__(64) void k_sweep_glb(SweepParams p) {
@@ -363,13 +581,26 @@ static bool compiled_size(int L) {
     }
 }
 
-SizePlan plan_sweeps(const SizeDev &s, int cpb) {
+SizePlan plan_sweeps(const SizeDev &s, int cpb, bool allow_pc) {
     SizePlan p{};
     p.cpb = cpb < 1 ? 1 : (cpb > 64 ? 64 : cpb);
+    p.R = 0;
     if (!compiled_size(s.L)) {
         p.kind = kSweepGeneric;
         p.cpb = 64;
         return p;
+    }
+    if (allow_pc && s.L <= 64 && s.L % 4 == 0) {
+        for (int R = 8; R >= 1; R /= 2) {
+            if (s.L % R) continue;
+            const PcLayout lay = pc_layout(s.L, s.W, s.N, s.n_bins, p.cpb, R);
+            if (lay.total <= kLdsMax) {
+                p.kind = kSweepPC;
+                p.R = R;
+                p.lds_bytes = lay.total;
+                return p;
+            }
+        }
     }
     const size_t lat_b = (size_t)s.L * s.W * p.cpb * 4;
     const size_t tab_b = (size_t)(s.N + 1) * 8 * 4;
@@ -387,7 +618,7 @@ SizePlan plan_sweeps(const SizeDev &s, int cpb) {
     return p;
 }
 
-bool batchable(const SizePlan &p) { return p.kind == kSweepLdsTab || p.kind == kSweepLds; }
+bool batchable(const SizePlan &p) { return p.kind == kSweepLdsTab || p.kind == kSweepLds || p.kind == kSweepPC; }
 
 // Raise a kernel's dynamic-LDS limit to at least `bytes` (never lower it: one
 // kernel can serve several sizes with different plans).
@@ -400,7 +631,8 @@ static hipError_t allow_lds(const void *kernel, size_t &allowed, size_t bytes) {
 
 template <int L>
 static hipError_t prepare_L(const SizePlan &p) {
-    static size_t allowed_tab = 0, allowed_notab = 0;
+    static size_t allowed_tab = 0, allowed_notab = 0, allowed_pc = 0;
+    if (p.kind == kSweepPC) return allow_lds((const void *)k_sweep_pc<L>, allowed_pc, p.lds_bytes);
     if (p.kind == kSweepLdsTab) return allow_lds((const void *)k_sweep_lds<L, true>, allowed_tab, p.lds_bytes);
     if (p.kind == kSweepLds) return allow_lds((const void *)k_sweep_lds<L, false>, allowed_notab, p.lds_bytes);
     return hipSuccess;
@@ -410,6 +642,11 @@ template <int L>
 static hipError_t launch_L(const SweepParams &p0, const SizePlan &pl, hipStream_t st) {
     SweepParams p = p0;
     const dim3 grid((p.s.P + pl.cpb - 1) / pl.cpb), block(64);
+    if (pl.kind == kSweepPC) {
+        PcParams q{p.s, p.M, p.trace, p.hist, pl.cpb, pl.R};
+        hipLaunchKernelGGL(k_sweep_pc<L>, grid, dim3(128), pl.lds_bytes, st, q);
+        return hipGetLastError();
+    }
     if (pl.kind == kSweepLdsTab) {
         p.lds_hist = 1;
         hipLaunchKernelGGL((k_sweep_lds<L, true>), grid, block, pl.lds_bytes, st, p);
@@ -472,6 +709,7 @@ struct BatchParams {
     int32_t *hist[kMaxSizes];
     int32_t cpb[kMaxSizes];
     int32_t kind[kMaxSizes];
+    int32_t R[kMaxSizes];
     const Tile *tiles;
     int32_t n_tiles;
     int32_t *counter;
@@ -480,13 +718,17 @@ struct BatchParams {
 
 template <int L>
 __device__ __forceinline__ void batched_tile(const BatchParams &p, int si, int c0, uint32_t *smem) {
-    if (p.kind[si] == kSweepLdsTab)
+    if (p.kind[si] == kSweepPC)
+        sweep_tile_pc<L>(p.sizes[si], c0, p.cpb[si], p.R[si], p.M, p.trace[si], p.hist[si], smem);
+    else if (p.kind[si] == kSweepLdsTab)
         sweep_tile_lds<L, true>(p.sizes[si], c0, p.cpb[si], p.M, p.trace[si], p.hist[si], true, smem);
     else
         sweep_tile_lds<L, false>(p.sizes[si], c0, p.cpb[si], p.M, p.trace[si], p.hist[si], true, smem);
 }
 
-__global__ __launch_bounds__(64) void k_sweep_batched(BatchParams p) {
+// 128 threads: the second wave produces random words for producer/consumer
+// tiles and idles on the others.
+__global__ __launch_bounds__(128) void k_sweep_batched(BatchParams p) {
     extern __shared__ uint32_t smem[];
     __shared__ int s_tile;
     for (;;) {
@@ -527,13 +769,14 @@ hipError_t launch_sweeps_batched(const SizeDev *sizes, const SizePlan *plans, in
         p.hist[i] = hist[i];
         p.cpb[i] = plans[i].cpb;
         p.kind[i] = plans[i].kind;
+        p.R[i] = plans[i].R;
     }
     p.tiles = tiles_dev;
     p.n_tiles = n_tiles;
     p.counter = counter_dev;
     p.M = M;
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, counter_dev);
-    hipLaunchKernelGGL(k_sweep_batched, dim3(grid), dim3(64), lds_bytes, st, p);
+    hipLaunchKernelGGL(k_sweep_batched, dim3(grid), dim3(128), lds_bytes, st, p);
     return hipGetLastError();
 }
 
