@@ -92,15 +92,27 @@ void free_size(SizeDev &d) {
     if (d.lev) (void)hipFree(d.lev);
     if (d.lnW) (void)hipFree(d.lnW);
     if (d.tab) (void)hipFree(d.tab);
+    if (d.tabc) (void)hipFree(d.tabc);
     if (d.ctl) (void)hipFree(d.ctl);
     if (d.scratch_cut) (void)hipFree(d.scratch_cut);
     d = SizeDev{};
 }
 
-// Default launch: the producer/consumer kernel with as many chains per
+// Default launch: for large lattices the streamed-row kernel with the per-bin
+// thresholds in LDS (32 chains per workgroup first), else with them in global
+// memory; otherwise the producer/consumer kernel with as many chains per
 // workgroup as fit in LDS, else the single-wave kernel with the thresholds in
 // LDS, else whatever fits.
 SizePlan default_plan(const SizeDev &d) {
+    if (d.L >= 128) {
+        const int order[4] = {32, 16, 64, 8};
+        for (int cpb : order) {
+            SizePlan q = plan_sweeps(d, cpb, true);
+            if (q.kind == kSweepBig) return q;
+        }
+        SizePlan q = plan_sweeps(d, 16, true);
+        if (q.kind == kSweepBigGlb) return q;
+    }
     for (int cpb = 64; cpb >= 8; cpb /= 2) {
         SizePlan q = plan_sweeps(d, cpb, true);
         if (q.kind == kSweepPC) return q;
@@ -222,10 +234,12 @@ mc_status mc_create(const mc_size *sizes, int32_t n_sizes, void *hip_stream, mc_
         d.n_bins = (d.N >> d.bin_shift) + 1;
         d.seed = h.cfg.seed;
         d.trace_bytes = (d.L <= 254) ? 2 : 4;
+        d.tab_r = d.bin_shift == 0 ? 2 : 1;
         const size_t lat_b = (size_t)d.L * d.W * d.P * 4;
         if (hipMalloc((void **)&d.lat, lat_b) != hipSuccess || hipMalloc((void **)&d.lev, (size_t)d.P * 4) != hipSuccess ||
             hipMalloc((void **)&d.lnW, (size_t)d.n_bins * 8) != hipSuccess ||
             hipMalloc((void **)&d.tab, (size_t)(d.N + 1) * 8 * 4) != hipSuccess ||
+            hipMalloc((void **)&d.tabc, (size_t)d.n_bins * (2 * d.tab_r + 1) * 4) != hipSuccess ||
             hipMalloc((void **)&d.ctl, sizeof(Ctl)) != hipSuccess ||
             hipMalloc((void **)&d.scratch_cut, (size_t)d.P * 4) != hipSuccess) {
             (void)hipGetLastError();

@@ -29,6 +29,8 @@ struct SizeDev {
     int32_t *lev;           // [P] current level of each chain
     double *lnW;            // [n_bins]
     uint32_t *tab;          // [(N+1)*8] thresholds, entry (m, a) at m*8 + a, a = dm + 2
+    uint32_t *tabc;         // [n_bins*(2*tab_r+1)] the same thresholds per bin (k_tabulate_compact)
+    int32_t tab_r;          // 2 with one level per bin, else 1
     Ctl *ctl;
     int32_t *scratch_cut;   // [P] speculative cut points of the joint
 };
@@ -39,13 +41,15 @@ enum SweepKind : int32_t {
     kSweepLds = 1,      // lattice in LDS, thresholds read from global memory
     kSweepGlobal = 2,   // lattice rows streamed from global memory (large L)
     kSweepGeneric = 3,  // any even L, bit by bit (L not among the compiled sizes)
-    kSweepPC = 4,       // lattice and thresholds in LDS, random words from a producer wave
+    kSweepPC = 4,       // lattice and thresholds in LDS, random words from producer waves
+    kSweepBig = 5,      // L >= 128: rows streamed from global memory, per-bin thresholds in LDS
+    kSweepBigGlb = 6,   // the same with the per-bin thresholds read from global memory
 };
 
 struct SizePlan {
     int32_t cpb;        // chains per 64-lane block
     int32_t kind;       // SweepKind
-    int32_t R;          // rows per chunk of random words (kSweepPC)
+    int32_t R;          // rows per chunk of random words (producer/consumer kinds)
     size_t lds_bytes;   // dynamic LDS per block
 };
 

@@ -73,9 +73,29 @@ __global__ void k_tabulate(SizeDev s) {
     }
 }
 
+// The same thresholds per bin (used by the large-lattice sweeps): bin b has
+// K = 2r + 1 entries, entry j for a move into bin b + j - r (a flip changes the
+// level by at most 2, so r = 2 with one level per bin and r = 1 otherwise).
+// The threshold of a move from level m to m' is entry K (m >> bs) +
+// (m' >> bs) - (m >> bs) + r, at byte 4 r + 8 r (m >> bs) + 4 (m' >> bs).
+// Entries of bins outside [0, n_bins) are 0 and never used.
+__global__ void k_tabulate_compact(SizeDev s) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= s.n_bins) return;
+    const int r = s.tab_r, K = 2 * r + 1;
+    const double w0 = s.lnW[b];
+    for (int j = 0; j < K; ++j) {
+        const int bt = b + j - r;
+        uint32_t t = 0u;
+        if (bt >= 0 && bt < s.n_bins) t = tau_of(s.lnW[bt] - w0);
+        s.tabc[(size_t)b * K + j] = t;
+    }
+}
+
 hipError_t launch_tabulate(const SizeDev &s, hipStream_t st) {
     const int bs = 256;
     hipLaunchKernelGGL(k_tabulate, dim3((s.N + 1 + bs - 1) / bs), dim3(bs), 0, st, s);
+    hipLaunchKernelGGL(k_tabulate_compact, dim3((s.n_bins + bs - 1) / bs), dim3(bs), 0, st, s);
     return hipGetLastError();
 }
 
@@ -262,38 +282,35 @@ __global__ __launch_bounds__(64) void k_sweep_lds(SweepParams p) {
 // Producer/consumer sweeps (L <= 64).  A chain's attempts are strictly serial,
 // so a chain advances at most one instruction of its wave per issue slot; the
 // random words, which do not depend on the chain, are therefore generated by
-// a second wave of the workgroup (on another SIMD) into an LDS double buffer,
+// the other waves of the workgroup (on other SIMDs) into an LDS double buffer,
 // R rows of every chain at a time, while the first wave consumes the previous
-// R rows.  The two waves meet at one barrier per chunk.
+// R rows.  The waves meet at one barrier per chunk.
 //
 // LDS layout (bytes, 16-aligned parts):
 //   [L*W*cpb u32]            lattice words, word (row*W + w) of chain l at (row*W+w)*cpb + l
-//   [(N+1)*8 u32]            thresholds
+//   [(N+1)*5 u32]            thresholds, entry a of level m at 5m + a
 //   [n_bins i32]             histogram
+//   [64 uint4]               site-pair table (pair_table)
 //   [2][R][L/4][cpb] uint4   random words, group q of row r of chain l
 // ---------------------------------------------------------------------------
 __host__ __device__ constexpr size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
 
+// Bytes per level of the LDS threshold table.
+constexpr int kLevelBytes = 20;
+
 struct PcLayout {
-    size_t lat, tab, hist, ubuf, total;
+    size_t lat, tab, hist, pair, ubuf, total;
 };
 
 __host__ __device__ inline PcLayout pc_layout(int L, int W, int N, int n_bins, int cpb, int R) {
     PcLayout o;
     o.lat = 0;
     o.tab = align16((size_t)L * W * cpb * 4);
-    o.hist = o.tab + align16((size_t)(N + 1) * 8 * 4);
-    o.ubuf = o.hist + align16((size_t)n_bins * 4);
+    o.hist = o.tab + align16((size_t)(N + 1) * kLevelBytes);
+    o.pair = o.hist + align16((size_t)n_bins * 4);
+    o.ubuf = o.pair + 64 * 16;
     o.total = o.ubuf + (size_t)2 * R * (L / 4) * cpb * 16;
     return o;
-}
-
-// a * b + c on 24-bit signed factors in one instruction (the backend would
-// otherwise emit a shift and a subtract).  Pure ALU.
-__device__ __forceinline__ uint32_t mad_i24(uint32_t a, int32_t b, uint32_t c) {
-    uint32_t r;
-    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
-    return r;
 }
 
 typedef __attribute__((address_space(3))) const uint32_t lds_u32;
@@ -301,16 +318,63 @@ typedef __attribute__((address_space(3))) const uint32_t lds_u32;
 // Read a 32-bit word at a byte address of LDS.
 __device__ __forceinline__ uint32_t lds_load(uint32_t addr) { return *(lds_u32 *)(size_t)addr; }
 
-// One row of the consumer.  `lds` is the LDS base; mib is the byte address in
-// LDS of entry (m, 4) of the threshold table, i.e. tab + 4 (8m + 4), so the
-// threshold of a flip with `anti` anti-aligned neighbours is at mib - 4 anti and
-// an accepted flip moves mib by 4 (16 - 8 anti).  P0, P1 hold per site the
-// two bits of xu + xd + (right bond), all at row start.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) const u32x4 lds_u32x4;
+
+// Read 16 bytes at a (16-aligned) byte address of LDS.
+__device__ __forceinline__ uint4 lds_load128(uint32_t addr) {
+    const u32x4 v = *(lds_u32x4 *)(size_t)addr;
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+// Signed byte k of w.
+__device__ __forceinline__ int32_t sbyte(uint32_t w, int k) { return (int32_t)(w << (24 - 8 * k)) >> 24; }
+
+// Site-pair table.  The consumer decides sites x and x+1 (x even) together.
+// With q = (up bond) + (down bond) + (right bond) broken at row start and h the
+// left bond at row start, site x has anti = q_x + (h_x ^ a) anti-aligned
+// neighbours, a = 1 iff its left neighbour x-1 flipped just before, and site
+// x+1 has an0 = q_{x+1} + h_{x+1} or an1 = q_{x+1} + (h_{x+1} ^ 1) after x was
+// rejected or accepted.  Entry i, for i = P0_x | P0_{x+1} << 1 | P1_x << 2 |
+// P1_{x+1} << 3 | h_x << 4 | h_{x+1} << 5 (q = P0 + 2 P1), holds as signed bytes
+// the byte offsets, from the threshold address of the current level (entry
+// a = 4 of that level), of
+//   .x = { threshold of x+1 if x rejected, 0, 0, level move if only x+1 accepted }
+//   .y = { threshold of x, threshold of x+1 if x accepted, level move if only x
+//          accepted, level move if both accepted }  for a = 0
+//   .z = the same for a = 1.
+__device__ void build_pair_table(uint4 *tbl, int tid, int nthreads) {
+    auto pack = [](int b0, int b1, int b2, int b3) {
+        return (uint32_t)(b0 & 255) | ((uint32_t)(b1 & 255) << 8) | ((uint32_t)(b2 & 255) << 16) |
+               ((uint32_t)(b3 & 255) << 24);
+    };
+    for (int i = tid; i < 64; i += nthreads) {
+        const int qx = (i & 1) + 2 * ((i >> 2) & 1);
+        const int qx1 = ((i >> 1) & 1) + 2 * ((i >> 3) & 1);
+        const int hx = (i >> 4) & 1, hx1 = (i >> 5) & 1;
+        const int an0 = qx1 + hx1, an1 = qx1 + (hx1 ^ 1);
+        uint32_t v[2];
+        for (int a = 0; a < 2; ++a) {
+            const int ax = qx + (hx ^ a);
+            const int dx = kLevelBytes * (2 - ax);
+            v[a] = pack(-4 * ax, dx - 4 * an1, dx, dx + kLevelBytes * (2 - an1));
+        }
+        tbl[i] = make_uint4(pack(-4 * an0, 0, 0, kLevelBytes * (2 - an0)), v[0], v[1], 0u);
+    }
+}
+
+// One row of the consumer, two sites at a time.  mib is the LDS byte address of
+// entry a = 4 of the current level of the threshold table, so the threshold of
+// a flip with `anti` anti-aligned neighbours is at mib - 4 anti and an accepted
+// flip moves mib by kLevelBytes (2 - anti).  The three thresholds a pair can
+// need are read at once from the level at the start of the pair; the two
+// decisions then only select.
 template <int L>
 __device__ __forceinline__ void pc_row(Row<L> &cur, const Row<L> &up, const Row<L> &dn, uint32_t &mib,
-                                       const char *lds, const uint4 *urow, int cpb) {
+                                       uint32_t pair_addr, const uint4 *urow, int cpb) {
     constexpr int W = (L + 31) / 32;
-    Row<L> xu, xd, hb, P0, P1;
+    constexpr int wl = (L - 1) >> 5, bl = (L - 1) & 31;
+    Row<L> xu, xd, hb, P0, P1, hs, fl;
     const Row<L> nx = ring_next<L>(cur);
 #pragma unroll
     for (int w = 0; w < W; ++w) {
@@ -319,60 +383,85 @@ __device__ __forceinline__ void pc_row(Row<L> &cur, const Row<L> &up, const Row<
         hb.w[w] = cur.w[w] ^ nx.w[w];
         P0.w[w] = __builtin_amdgcn_bitop3_b32(xu.w[w], xd.w[w], hb.w[w], 0x96);  // parity
         P1.w[w] = __builtin_amdgcn_bitop3_b32(xu.w[w], xd.w[w], hb.w[w], 0xE8);  // majority
+        fl.w[w] = 0u;
     }
-    int anti = (int)(bit_at<L>(xu, 0) + bit_at<L>(xd, 0) + bit_at<L>(hb, 0) + bit_at<L>(hb, L - 1));
-    uint32_t t = lds_load(mad_i24((uint32_t)anti, -4, mib));
-    uint32_t mibD = mib + mad_i24((uint32_t)anti, -32, 64u);
-    uint32_t f0 = 0;
-    uint4 u4 = urow[0], unext = u4;
+    // hs: bit x is the left bond of site x, i.e. bond (x-1, x), cyclically
 #pragma unroll
-    for (int x = 0; x < L; ++x) {
-        if ((x & 3) == 0) {
-            u4 = unext;
-            if (x + 4 < L) unext = urow[((x >> 2) + 1) * cpb];
+    for (int w = 0; w < W; ++w) hs.w[w] = (hb.w[w] << 1) | (w > 0 ? hb.w[w - 1] >> 31 : 0u);
+    hs.w[0] |= (hb.w[wl] >> bl) & 1u;
+    auto entry = [&](int p) {
+        const int w = (2 * p) >> 5, b = (2 * p) & 31;
+        const uint32_t idx =
+            ((P0.w[w] >> b) & 3u) | (((P1.w[w] >> b) & 3u) << 2) | (((hs.w[w] >> b) & 3u) << 4);
+        return lds_load128(pair_addr + idx * 16u);
+    };
+    bool aprev = false;
+    uint4 u4 = make_uint4(0, 0, 0, 0);
+    uint4 en = entry(0);
+#pragma unroll
+    for (int p = 0; p < L / 2; ++p) {
+        const int x = 2 * p, w = x >> 5, b = x & 31;
+        if (p == 1) {
+            // the right neighbour of site L-1 is site 0, decided in the first pair
+            const uint32_t hl = hb.w[wl] ^ ((fl.w[0] & 1u) << bl);
+            P0.w[wl] = __builtin_amdgcn_bitop3_b32(xu.w[wl], xd.w[wl], hl, 0x96);
+            P1.w[wl] = __builtin_amdgcn_bitop3_b32(xu.w[wl], xd.w[wl], hl, 0xE8);
         }
-        const uint32_t u = (x & 3) == 0 ? u4.x : (x & 3) == 1 ? u4.y : (x & 3) == 2 ? u4.z : u4.w;
-        uint32_t an0 = 0, an1 = 0;
-        uint32_t t0n = 0, t1n = 0;
-        if (x + 1 < L) {
-            const int xn = x + 1;
-            const uint32_t h = bit_at<L>(hb, x);  // bond (x, x+1) at row start
-            uint32_t q;
-            if (xn == L - 1)  // its right neighbour is site 0, decided at the start of the row
-                q = bit_at<L>(xu, xn) + bit_at<L>(xd, xn) + (bit_at<L>(hb, xn) ^ f0);
-            else
-                q = bit_at<L>(P0, xn) + 2 * bit_at<L>(P1, xn);
-            an0 = q + h;
-            an1 = q + (h ^ 1u);
-            t0n = lds_load(mad_i24(an0, -4, mib));
-            t1n = lds_load(mad_i24(an1, -4, mibD));
-        }
-        const bool acc = u <= t;
-        if (x == 0) f0 = acc ? 1u : 0u;
-        cur.w[x >> 5] ^= (acc ? 1u : 0u) << (x & 31);
-        mib = acc ? mibD : mib;
-        if (x + 1 < L) {
-            anti = (int)(acc ? an1 : an0);
-            t = acc ? t1n : t0n;
-            mibD = mib + mad_i24((uint32_t)anti, -32, 64u);
-        }
+        // entries are read one pair ahead; with two pairs per row the last one
+        // is read again after the fix above
+        const uint4 e = (L / 2 == 2 && p == 1) ? entry(1) : en;
+        if (p + 1 < L / 2) en = entry(p + 1);
+        if ((p & 1) == 0) u4 = urow[(p >> 1) * cpb];
+        const uint32_t ux = (p & 1) ? u4.z : u4.x;
+        const uint32_t ux1 = (p & 1) ? u4.w : u4.y;
+        const uint32_t V = aprev ? e.z : e.y;
+        const uint32_t tx = lds_load(mib + sbyte(V, 0));
+        const uint32_t t0 = lds_load(mib + sbyte(e.x, 0));
+        const uint32_t t1 = lds_load(mib + sbyte(V, 1));
+        const uint32_t m10 = mib + sbyte(V, 2), m11 = mib + sbyte(V, 3), m01 = mib + sbyte(e.x, 3);
+        const bool ax = ux <= tx;
+        const uint32_t tn = ax ? t1 : t0;
+        const uint32_t mA = ax ? m11 : m01, mB = ax ? m10 : mib;
+        const bool ax1 = ux1 <= tn;
+        mib = ax1 ? mA : mB;
+        fl.w[w] |= (ax ? 1u << b : 0u) | (ax1 ? 2u << b : 0u);
+        aprev = ax1;
     }
+#pragma unroll
+    for (int w = 0; w < W; ++w) cur.w[w] ^= fl.w[w];
 }
 
 // Random words of one chunk: rows y0 .. y0+R-1 of sweep g for every chain of
-// the block.  Producer thread `pt` of `np` threads.
+// the block, item it = rq * cpb + l (word group rq of the chunk, chain l).
+// Producer thread pt of np takes items pt, pt + np, ..., two independent
+// Philox calls at a time; lanes whose chain is beyond P write words that are
+// never read.
 template <int L>
-__device__ __forceinline__ void pc_produce(uint4 *ub, int R, uint32_t y0, uint32_t g, int c0, int cpb, int P,
+__device__ __forceinline__ void pc_produce(uint4 *ub, int R, uint32_t y0, uint32_t g, int c0, int cpb,
                                            uint32_t k0, uint32_t k1, int pt, int np) {
     constexpr int NQ = L / 4;
     const int items = R * NQ * cpb;
-    for (int it = pt; it < items; it += np) {
-        const int l = it % cpb;
-        const int rq = it / cpb;  // r * NQ + q
-        const uint32_t c = (uint32_t)(c0 + l);
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if ((int)c < P) v = philox10(make_uint4(y0 * (uint32_t)NQ + (uint32_t)rq, g, c, kDomSweep), k0, k1);
-        ub[it] = v;
+    const int dl = np % cpb, drq = np / cpb;
+    int l = pt % cpb, rq = pt / cpb;
+    const uint32_t ctr0 = y0 * (uint32_t)NQ;
+    auto step = [&](int &ll, int &rr) {
+        ll += dl;
+        rr += drq;
+        if (ll >= cpb) {
+            ll -= cpb;
+            ++rr;
+        }
+    };
+    for (int it = pt; it < items; it += 2 * np) {
+        int l1 = l, rq1 = rq;
+        step(l1, rq1);
+        const uint4 v0 = philox10(make_uint4(ctr0 + (uint32_t)rq, g, (uint32_t)(c0 + l), kDomSweep), k0, k1);
+        const uint4 v1 = philox10(make_uint4(ctr0 + (uint32_t)rq1, g, (uint32_t)(c0 + l1), kDomSweep), k0, k1);
+        ub[it] = v0;
+        if (it + np < items) ub[it + np] = v1;
+        l = l1;
+        rq = rq1;
+        step(l, rq);
     }
 }
 
@@ -396,6 +485,7 @@ __device__ __forceinline__ void sweep_tile_pc(const SizeDev &s, int c0, int cpb,
     uint32_t *slat = (uint32_t *)(lds + lay.lat);
     uint32_t *stab = (uint32_t *)(lds + lay.tab);
     int32_t *shist = (int32_t *)(lds + lay.hist);
+    uint4 *ptbl = (uint4 *)(lds + lay.pair);
     uint4 *ubuf = (uint4 *)(lds + lay.ubuf);
     const int chunk_words = R * (L / 4) * cpb;  // uint4 per buffer
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -404,21 +494,26 @@ __device__ __forceinline__ void sweep_tile_pc(const SizeDev &s, int c0, int cpb,
     const bool active = consumer && lane < cpb && c < s.P;
     const uint32_t k0 = s.seed, k1 = (uint32_t)L;
     const uint32_t g0 = s.ctl->g;
-    for (int i = threadIdx.x; i < (N + 1) * 8; i += blockDim.x) stab[i] = s.tab[i];
+    for (int i = threadIdx.x; i < (N + 1) * 5; i += blockDim.x) {
+        const int m = i / 5;
+        stab[i] = s.tab[(size_t)m * 8 + (i - 5 * m)];
+    }
     for (int i = threadIdx.x; i < s.n_bins; i += blockDim.x) shist[i] = 0;
+    build_pair_table(ptbl, threadIdx.x, blockDim.x);
     if (active)
         for (int w = 0; w < L * W; ++w) slat[w * cpb + lane] = s.lat[(size_t)w * s.P + c];
     const int np = blockDim.x - 64, pt = threadIdx.x - 64;
     const int per_sweep = L / R;
     const int64_t n_chunks = M * per_sweep;
-    if (!consumer) pc_produce<L>(ubuf, R, 0u, g0, c0, cpb, s.P, k0, k1, pt, np);
+    if (!consumer) pc_produce<L>(ubuf, R, 0u, g0, c0, cpb, k0, k1, pt, np);
     __syncthreads();
 
     uint32_t mib = 0;
     Row<L> up, cur, dn;
     // absolute LDS byte address (dynamic LDS starts at address 0 of the workgroup's LDS)
     const uint32_t tab_addr = (uint32_t)(size_t)(lds_u32 *)(stab);
-    if (active) mib = tab_addr + 4u * (8u * (uint32_t)s.lev[c] + 4u);
+    const uint32_t pair_addr = (uint32_t)(size_t)(lds_u32 *)(ptbl);
+    if (active) mib = tab_addr + (uint32_t)kLevelBytes * (uint32_t)s.lev[c] + 16u;
     for (int64_t i = 0; i < n_chunks; ++i) {
         const int64_t k = i / per_sweep;
         const int y0 = (int)(i - k * per_sweep) * R;
@@ -437,7 +532,7 @@ __device__ __forceinline__ void sweep_tile_pc(const SizeDev &s, int c0, int cpb,
             }
             for (int r = 0; r < R; ++r) {
                 const int y = y0 + r;
-                pc_row<L>(cur, up, dn, mib, lds, ub + (size_t)r * (L / 4) * cpb + lane, cpb);
+                pc_row<L>(cur, up, dn, mib, pair_addr, ub + (size_t)r * (L / 4) * cpb + lane, cpb);
 #pragma unroll
                 for (int w = 0; w < W; ++w) slat[(y * W + w) * cpb + lane] = cur.w[w];
                 up = cur;
@@ -445,7 +540,7 @@ __device__ __forceinline__ void sweep_tile_pc(const SizeDev &s, int c0, int cpb,
                 dn = load(y + 2 < L ? y + 2 : y + 2 - L);
             }
             if (y0 + R == L) {
-                const int m = (int)((mib - tab_addr - 16u) >> 5);
+                const int m = (int)((mib - tab_addr - 16u) / (uint32_t)kLevelBytes);
                 const int ev = m - N / 2;
                 if (s.trace_bytes == 2)
                     ((int16_t *)trace)[(size_t)c * M + k] = (int16_t)ev;
@@ -457,12 +552,12 @@ __device__ __forceinline__ void sweep_tile_pc(const SizeDev &s, int c0, int cpb,
             const int64_t k1s = (i + 1) / per_sweep;
             const int y1 = (int)(i + 1 - k1s * per_sweep) * R;
             pc_produce<L>(ubuf + (size_t)((i + 1) & 1) * chunk_words, R, (uint32_t)y1, g0 + (uint32_t)k1s, c0, cpb,
-                          s.P, k0, k1, pt, np);
+                          k0, k1, pt, np);
         }
         __syncthreads();
     }
     if (active) {
-        s.lev[c] = (int)((mib - tab_addr - 16u) >> 5);
+        s.lev[c] = (int)((mib - tab_addr - 16u) / (uint32_t)kLevelBytes);
         for (int w = 0; w < L * W; ++w) s.lat[(size_t)w * s.P + c] = slat[w * cpb + lane];
     }
     for (int i = threadIdx.x; i < s.n_bins; i += blockDim.x)
@@ -470,10 +565,207 @@ __device__ __forceinline__ void sweep_tile_pc(const SizeDev &s, int c0, int cpb,
     __syncthreads();
 }
 
+// 256 threads: one consumer wave and three producer waves.
+constexpr int kPcThreads = 256;
+
 template <int L>
-__global__ __launch_bounds__(128) void k_sweep_pc(PcParams p) {
+__global__ __launch_bounds__(kPcThreads) void k_sweep_pc(PcParams p) {
     extern __shared__ uint32_t smem[];
     sweep_tile_pc<L>(p.s, blockIdx.x * p.cpb, p.cpb, p.R, p.M, p.trace, p.hist, smem);
+}
+
+// ---------------------------------------------------------------------------
+// Large lattices (L = 128, 256): the producer/consumer scheme with each row
+// streamed from global memory one 32-bit word at a time (the next word is read
+// while the current one is swept) and the thresholds in the compact per-bin
+// table, held in LDS when it fits (TAB_LDS) and read from global memory
+// otherwise.
+//
+// LDS layout (bytes):
+//   [n_bins*(2r+1) u32]      compact thresholds (TAB_LDS)
+//   [64 uint4]               site-pair table in level units (pair_levels)
+//   [2][R][L/4][cpb] uint4   random words, as for the producer/consumer kernel
+// ---------------------------------------------------------------------------
+struct BigLayout {
+    size_t tab, pair, ubuf, total;
+};
+
+__host__ __device__ inline BigLayout big_layout(int L, int n_bins, int r, int cpb, int R, bool tab_lds) {
+    BigLayout o;
+    o.tab = 0;
+    o.pair = tab_lds ? align16((size_t)n_bins * (2 * r + 1) * 4) : 0;
+    o.ubuf = o.pair + 64 * 16;
+    o.total = o.ubuf + (size_t)2 * R * (L / 4) * cpb * 16;
+    return o;
+}
+
+// The site-pair table of pair_table with level changes instead of byte
+// offsets: for d = 2 - anti (the level change of a flip),
+//   .x = { d of x+1 if x rejected }
+//   .y = { d of x, (d of x) + (d of x+1 if x accepted) }  for a = 0
+//   .z = the same for a = 1.
+__device__ void build_pair_levels(uint4 *tbl, int tid, int nthreads) {
+    auto pack = [](int b0, int b1) { return (uint32_t)(b0 & 255) | ((uint32_t)(b1 & 255) << 8); };
+    for (int i = tid; i < 64; i += nthreads) {
+        const int qx = (i & 1) + 2 * ((i >> 2) & 1);
+        const int qx1 = ((i >> 1) & 1) + 2 * ((i >> 3) & 1);
+        const int hx = (i >> 4) & 1, hx1 = (i >> 5) & 1;
+        const int d0 = 2 - (qx1 + hx1), d1 = 2 - (qx1 + (hx1 ^ 1));
+        uint32_t v[2];
+        for (int a = 0; a < 2; ++a) {
+            const int dx = 2 - (qx + (hx ^ a));
+            v[a] = pack(dx, dx + d1);
+        }
+        tbl[i] = make_uint4(pack(d0, 0), v[0], v[1], 0u);
+    }
+}
+
+// Thresholds of the compact table at a byte offset: from LDS (the offset is an
+// absolute LDS address) or from global memory (relative to tabc).
+template <bool TAB_LDS>
+__device__ __forceinline__ uint32_t big_threshold(const uint32_t *tabc, uint32_t off) {
+    if (TAB_LDS) return lds_load(off);
+    return *(const uint32_t *)((const char *)tabc + off);
+}
+
+// One row of a large lattice.  State: m, the level, and Bm = B0 + 8 r (m >> bs),
+// the byte offset of bin m >> bs in the compact table plus 4 r, so that the
+// threshold of a move to level m' is at Bm + 4 (m' >> bs).
+template <int L, bool TAB_LDS>
+__device__ __forceinline__ void big_row(uint32_t *lat, size_t P, int c, int y, int &m, uint32_t &Bm, int bs,
+                                        uint32_t B0, int sB, const uint32_t *tabc, uint32_t pair_addr,
+                                        const uint4 *urow, int cpb) {
+    constexpr int W = L / 32;
+    const int yu = y == 0 ? L - 1 : y - 1, yd = y + 1 == L ? 0 : y + 1;
+    auto word = [&](int yy, int w) { return lat + (size_t)(yy * W + w) * P + c; };
+    uint32_t cn = *word(y, 0), un = *word(yu, 0), dn = *word(yd, 0), cnn = *word(y, 1);
+    // bond (L-1, 0) at row start: the left bond of site 0
+    uint32_t carry = ((*word(y, W - 1) >> 31) ^ cn) & 1u;
+    uint32_t c0new = 0u;
+    bool aprev = false;
+    for (int w = 0; w < W; ++w) {
+        const uint32_t cw = cn, uw = un, dw = dn;
+        // right neighbours of the word; for the last word bit 31 is site 0 as
+        // it is now (it was decided at the start of the row)
+        const uint32_t cw1 = w + 1 < W ? cnn : c0new;
+        if (w + 1 < W) {
+            cn = cnn;
+            un = *word(yu, w + 1);
+            dn = *word(yd, w + 1);
+            if (w + 2 < W) cnn = *word(y, w + 2);
+        }
+        const uint32_t xu = cw ^ uw, xd = cw ^ dw, hb = cw ^ ((cw >> 1) | (cw1 << 31));
+        const uint32_t P0 = __builtin_amdgcn_bitop3_b32(xu, xd, hb, 0x96);
+        const uint32_t P1 = __builtin_amdgcn_bitop3_b32(xu, xd, hb, 0xE8);
+        const uint32_t hs = (hb << 1) | carry;  // left bonds
+        carry = hb >> 31;
+        const uint4 *uw4 = urow + (size_t)w * 8 * cpb;
+        auto entry = [&](int p) {
+            const uint32_t idx = ((P0 >> (2 * p)) & 3u) | (((P1 >> (2 * p)) & 3u) << 2) | (((hs >> (2 * p)) & 3u) << 4);
+            return lds_load128(pair_addr + idx * 16u);
+        };
+        uint32_t fw = 0u;
+        uint4 u4 = make_uint4(0, 0, 0, 0);
+        uint4 en = entry(0);
+#pragma unroll
+        for (int p = 0; p < 16; ++p) {
+            const uint4 e = en;
+            if (p + 1 < 16) en = entry(p + 1);
+            if ((p & 1) == 0) u4 = uw4[(p >> 1) * cpb];
+            const uint32_t ux = (p & 1) ? u4.z : u4.x;
+            const uint32_t ux1 = (p & 1) ? u4.w : u4.y;
+            const uint32_t V = aprev ? e.z : e.y;
+            const int mx = m + sbyte(V, 0), m0 = m + sbyte(e.x, 0), m11 = m + sbyte(V, 1);
+            const uint32_t bx = (uint32_t)(mx >> bs), b0 = (uint32_t)(m0 >> bs), b11 = (uint32_t)(m11 >> bs);
+            const uint32_t Bx = B0 + (bx << sB), Bb0 = B0 + (b0 << sB), B11 = B0 + (b11 << sB);
+            const uint32_t tx = big_threshold<TAB_LDS>(tabc, Bm + 4u * bx);
+            const uint32_t t0 = big_threshold<TAB_LDS>(tabc, Bm + 4u * b0);
+            const uint32_t t1 = big_threshold<TAB_LDS>(tabc, Bx + 4u * b11);
+            const bool ax = ux <= tx;
+            const uint32_t tn = ax ? t1 : t0;
+            const int mA = ax ? m11 : m0, mB = ax ? mx : m;
+            const uint32_t BA = ax ? B11 : Bb0, BB = ax ? Bx : Bm;
+            const bool ax1 = ux1 <= tn;
+            m = ax1 ? mA : mB;
+            Bm = ax1 ? BA : BB;
+            fw |= (ax ? 1u << (2 * p) : 0u) | (ax1 ? 2u << (2 * p) : 0u);
+            aprev = ax1;
+        }
+        const uint32_t cnew = cw ^ fw;
+        *word(y, w) = cnew;
+        if (w == 0) c0new = cnew;
+    }
+}
+
+// Sweeps of chains c0 .. c0+cpb-1 of a large lattice; wave 0 consumes, the
+// other waves produce random words.
+template <int L, bool TAB_LDS>
+__device__ __forceinline__ void sweep_tile_big(const SizeDev &s, int c0, int cpb, int R, int64_t M, void *trace,
+                                               int32_t *hist, uint32_t *smem) {
+    constexpr int N = L * L;
+    const int r = s.tab_r, K = 2 * r + 1;
+    const BigLayout lay = big_layout(L, s.n_bins, r, cpb, R, TAB_LDS);
+    char *lds = (char *)smem;
+    uint32_t *stab = (uint32_t *)(lds + lay.tab);
+    uint4 *ptbl = (uint4 *)(lds + lay.pair);
+    uint4 *ubuf = (uint4 *)(lds + lay.ubuf);
+    const int chunk_words = R * (L / 4) * cpb;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int c = c0 + lane;
+    const bool consumer = wave == 0;
+    const bool active = consumer && lane < cpb && c < s.P;
+    const uint32_t k0 = s.seed, k1 = (uint32_t)L;
+    const uint32_t g0 = s.ctl->g;
+    if (TAB_LDS)
+        for (int i = threadIdx.x; i < s.n_bins * K; i += blockDim.x) stab[i] = s.tabc[i];
+    build_pair_levels(ptbl, threadIdx.x, blockDim.x);
+    const int np = blockDim.x - 64, pt = threadIdx.x - 64;
+    const int per_sweep = L / R;
+    const int64_t n_chunks = M * per_sweep;
+    if (!consumer) pc_produce<L>(ubuf, R, 0u, g0, c0, cpb, k0, k1, pt, np);
+    __syncthreads();
+
+    const uint32_t B0 = (TAB_LDS ? (uint32_t)(size_t)(lds_u32 *)(stab) : 0u) + 4u * (uint32_t)r;
+    const int sB = r == 1 ? 3 : 4;  // log2(8 r)
+    const int bs = s.bin_shift;
+    const uint32_t pair_addr = (uint32_t)(size_t)(lds_u32 *)(ptbl);
+    int m = 0;
+    uint32_t Bm = 0u;
+    if (active) {
+        m = s.lev[c];
+        Bm = B0 + ((uint32_t)(m >> bs) << sB);
+    }
+    for (int64_t i = 0; i < n_chunks; ++i) {
+        const int64_t k = i / per_sweep;
+        const int y0 = (int)(i - k * per_sweep) * R;
+        if (active) {
+            const uint4 *ub = ubuf + (size_t)(i & 1) * chunk_words;
+            for (int rr = 0; rr < R; ++rr)
+                big_row<L, TAB_LDS>(s.lat, (size_t)s.P, c, y0 + rr, m, Bm, bs, B0, sB, s.tabc, pair_addr,
+                                    ub + (size_t)rr * (L / 4) * cpb + lane, cpb);
+            if (y0 + R == L) {
+                const int ev = m - N / 2;
+                if (s.trace_bytes == 2)
+                    ((int16_t *)trace)[(size_t)c * M + k] = (int16_t)ev;
+                else
+                    ((int32_t *)trace)[(size_t)c * M + k] = ev;
+                atomicAdd(&hist[m >> bs], 1);
+            }
+        } else if (!consumer && i + 1 < n_chunks) {
+            const int64_t k1s = (i + 1) / per_sweep;
+            const int y1 = (int)(i + 1 - k1s * per_sweep) * R;
+            pc_produce<L>(ubuf + (size_t)((i + 1) & 1) * chunk_words, R, (uint32_t)y1, g0 + (uint32_t)k1s, c0, cpb,
+                          k0, k1, pt, np);
+        }
+        __syncthreads();
+    }
+    if (active) s.lev[c] = m;
+}
+
+template <int L, bool TAB_LDS>
+__global__ __launch_bounds__(kPcThreads) void k_sweep_big(PcParams p) {
+    extern __shared__ uint32_t smem[];
+    sweep_tile_big<L, TAB_LDS>(p.s, blockIdx.x * p.cpb, p.cpb, p.R, p.M, p.trace, p.hist, smem);
 }
 
 // Lattice rows streamed from global memory (large L); thresholds from global.
@@ -572,6 +864,8 @@ hipError_t launch_advance(const SizeDev &s, int64_t M, hipStream_t st) {
 // static LDS.
 constexpr size_t kLdsMax = 160 * 1024 - 256;
 
+static bool big_size(int L) { return L == 128 || L == 256; }
+
 static bool compiled_size(int L) {
     switch (L) {
     case 4: case 8: case 12: case 16: case 20: case 24: case 32: case 40: case 48: case 64: case 128: case 256:
@@ -589,6 +883,20 @@ SizePlan plan_sweeps(const SizeDev &s, int cpb, bool allow_pc) {
         p.kind = kSweepGeneric;
         p.cpb = 64;
         return p;
+    }
+    if (allow_pc && big_size(s.L)) {
+        for (int pass = 0; pass < 2; ++pass) {
+            const bool tab_lds = pass == 0;
+            for (int R = 4; R >= 1; R /= 2) {
+                const BigLayout lay = big_layout(s.L, s.n_bins, s.tab_r, p.cpb, R, tab_lds);
+                if (lay.total <= kLdsMax) {
+                    p.kind = tab_lds ? kSweepBig : kSweepBigGlb;
+                    p.R = R;
+                    p.lds_bytes = lay.total;
+                    return p;
+                }
+            }
+        }
     }
     if (allow_pc && s.L <= 64 && s.L % 4 == 0) {
         for (int R = 8; R >= 1; R /= 2) {
@@ -631,7 +939,12 @@ static hipError_t allow_lds(const void *kernel, size_t &allowed, size_t bytes) {
 
 template <int L>
 static hipError_t prepare_L(const SizePlan &p) {
-    static size_t allowed_tab = 0, allowed_notab = 0, allowed_pc = 0;
+    static size_t allowed_tab = 0, allowed_notab = 0, allowed_pc = 0, allowed_big = 0, allowed_bigg = 0;
+    if constexpr (L >= 128) {
+        if (p.kind == kSweepBig) return allow_lds((const void *)k_sweep_big<L, true>, allowed_big, p.lds_bytes);
+        if (p.kind == kSweepBigGlb)
+            return allow_lds((const void *)k_sweep_big<L, false>, allowed_bigg, p.lds_bytes);
+    }
     if (p.kind == kSweepPC) return allow_lds((const void *)k_sweep_pc<L>, allowed_pc, p.lds_bytes);
     if (p.kind == kSweepLdsTab) return allow_lds((const void *)k_sweep_lds<L, true>, allowed_tab, p.lds_bytes);
     if (p.kind == kSweepLds) return allow_lds((const void *)k_sweep_lds<L, false>, allowed_notab, p.lds_bytes);
@@ -642,9 +955,19 @@ template <int L>
 static hipError_t launch_L(const SweepParams &p0, const SizePlan &pl, hipStream_t st) {
     SweepParams p = p0;
     const dim3 grid((p.s.P + pl.cpb - 1) / pl.cpb), block(64);
+    if constexpr (L >= 128) {
+        if (pl.kind == kSweepBig || pl.kind == kSweepBigGlb) {
+            PcParams q{p.s, p.M, p.trace, p.hist, pl.cpb, pl.R};
+            if (pl.kind == kSweepBig)
+                hipLaunchKernelGGL((k_sweep_big<L, true>), grid, dim3(kPcThreads), pl.lds_bytes, st, q);
+            else
+                hipLaunchKernelGGL((k_sweep_big<L, false>), grid, dim3(kPcThreads), pl.lds_bytes, st, q);
+            return hipGetLastError();
+        }
+    }
     if (pl.kind == kSweepPC) {
         PcParams q{p.s, p.M, p.trace, p.hist, pl.cpb, pl.R};
-        hipLaunchKernelGGL(k_sweep_pc<L>, grid, dim3(128), pl.lds_bytes, st, q);
+        hipLaunchKernelGGL(k_sweep_pc<L>, grid, dim3(kPcThreads), pl.lds_bytes, st, q);
         return hipGetLastError();
     }
     if (pl.kind == kSweepLdsTab) {
@@ -726,9 +1049,9 @@ __device__ __forceinline__ void batched_tile(const BatchParams &p, int si, int c
         sweep_tile_lds<L, false>(p.sizes[si], c0, p.cpb[si], p.M, p.trace[si], p.hist[si], true, smem);
 }
 
-// 128 threads: the second wave produces random words for producer/consumer
-// tiles and idles on the others.
-__global__ __launch_bounds__(128) void k_sweep_batched(BatchParams p) {
+// kPcThreads threads: waves 1.. produce random words for producer/consumer
+// tiles and idle on the others.
+__global__ __launch_bounds__(kPcThreads) void k_sweep_batched(BatchParams p) {
     extern __shared__ uint32_t smem[];
     __shared__ int s_tile;
     for (;;) {
@@ -776,7 +1099,7 @@ hipError_t launch_sweeps_batched(const SizeDev *sizes, const SizePlan *plans, in
     p.counter = counter_dev;
     p.M = M;
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, counter_dev);
-    hipLaunchKernelGGL(k_sweep_batched, dim3(grid), dim3(128), lds_bytes, st, p);
+    hipLaunchKernelGGL(k_sweep_batched, dim3(grid), dim3(kPcThreads), lds_bytes, st, p);
     return hipGetLastError();
 }
 

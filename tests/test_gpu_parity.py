@@ -126,7 +126,7 @@ def test_L32_prior_weight_rounds_bitexact():
 
 @pytest.mark.parametrize("L,P,bs,M", [(4, 65, 0, 40), (6, 9, 1, 30), (10, 9, 0, 20), (12, 64, 1, 30),
                                       (16, 70, 1, 25), (24, 33, 1, 12), (48, 20, 1, 6), (64, 40, 1, 5),
-                                      (64, 7, 0, 4), (128, 5, 1, 2), (256, 2, 1, 1)])
+                                      (64, 7, 0, 4), (128, 5, 1, 2), (128, 9, 0, 2), (256, 20, 1, 1)])
 def test_sizes_and_binnings_bitexact(L, P, bs, M):
     mc = _mc()
     N = L * L
@@ -145,6 +145,38 @@ def test_sizes_and_binnings_bitexact(L, P, bs, M):
         assert_round_equal(g, o)
     assert_state_equal(ctx, R)
     ctx.close()
+
+
+def _smooth_weight(L, bs, seed):
+    N = L * L
+    nb = (N >> bs) + 1
+    rng = np.random.default_rng(seed)
+    x = (np.arange(nb) - nb / 2) / nb
+    return -0.25 * N * x * x + rng.normal(0, 0.3, nb)
+
+
+def test_large_lattice_kernels_bitexact():
+    """L = 128 with width-8 bins: the streamed-row kernel with the per-bin
+    thresholds in LDS (kind 5; 32 chains per workgroup by default, and 13) and
+    read from global memory (kind 6, 64 chains per workgroup do not leave room
+    for the table), each against the oracle over two rounds with a ragged
+    last workgroup."""
+    mc = _mc()
+    L, P, bs, M = 128, 70, 1, 2
+    w = _smooth_weight(L, bs, 11)
+    for cpb, kind in [(None, 5), (13, 5), (64, 6)]:
+        ctx = mc.Context([(L, P, 3, bs)])
+        ctx.init_weights(w)
+        if cpb is not None:
+            ctx.set_chains_per_block(cpb)
+        assert ctx.launch()[1] == kind, (cpb, ctx.launch())
+        R = O.Run(L, P, seed=3, bin_shift=bs, lnW=w)
+        for _ in range(2):
+            g = gpu_round(ctx, M)
+            o = oracle_round(R, M)
+            assert_round_equal(g, o)
+        assert_state_equal(ctx, R)
+        ctx.close()
 
 
 def test_join_hand_built_traces_and_modes():
