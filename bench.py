@@ -70,7 +70,7 @@ def kernel_source_hash():
 def traffic_from_profiles(L, P, M):
     """HBM bytes per sweep launch from the committed counter summary, if it was
     taken on the current kernel source and workload; else None."""
-    path = os.path.join(ROOT, "profiles", "k_sweep_L32_4096x1e5_counters.md")
+    path = os.path.join(ROOT, "profiles", "k_sweep_pc_L32_4096x1e5_counters.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -103,6 +103,11 @@ def base_record(a, value, ms_per_step, config, dtype="u32"):
     return {"metric": METRIC, "value": value, "unit": "spin-flip attempts/s", "n_gpus": 1, "steps": a.steps,
             "warmup": a.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+
+
+def kernel_name(kind, L):
+    return {0: "k_sweep_lds<%d,true>", 1: "k_sweep_lds<%d,false>", 2: "k_sweep_glb<%d>", 3: "k_sweep_generic",
+            4: "k_sweep_pc<%d>", 5: "k_sweep_big<%d,true>", 6: "k_sweep_big<%d,false>"}[kind].replace("%d", str(L))
 
 
 def roofline(attempts, kernel_s, traffic):
@@ -157,8 +162,7 @@ def bench_l32(a, torch, mc):
                        "L": L, "chains": P, "sweeps_per_step": M, "bins": ctx.n_bins(), "parallelism": "chains",
                        "chains_per_block": cpb, "kernel_kind": kind})
     res["roofline"] = roofline(att, sweep_s, traffic_from_profiles(L, P, M))
-    res["roofline"]["kernel"] = {0: "k_sweep_lds<32,true>", 1: "k_sweep_lds<32,false>", 2: "k_sweep_glb<32>",
-                                 3: "k_sweep_generic", 4: "k_sweep_pc<32>"}[kind] + " (mc_run_chains)"
+    res["roofline"]["kernel"] = kernel_name(kind, L) + " (mc_run_chains)"
     res["sweep_attempts_per_s"] = att / sweep_s
     ctx.close()
     if not a.no_cpu:
@@ -249,6 +253,7 @@ def bench_l128(a, torch, mc):
                       {"workload": "2D Ising L=128, %d chains x %d sweeps per step, ln w = 0 start" % (P, M),
                        "L": L, "chains": P, "sweeps_per_step": M, "kernel_kind": kind})
     res["roofline"] = roofline(att, sweep_s, None)
+    res["roofline"]["kernel"] = kernel_name(kind, L) + " (mc_run_chains)"
     return res
 
 
