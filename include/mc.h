@@ -158,17 +158,25 @@ mc_status mc_get_progress(mc_ctx *ctx, int32_t size_idx, int32_t *updates, int32
 
 /* Launch configuration.  Chains are independent, so the configuration
    changes speed only, never results.
-   mc_set_chains_per_block: chains per 64-lane workgroup (1..64) of one size.
-   mc_get_launch: chains per workgroup, kernel kind (0 lattice and thresholds
-   in LDS, 1 lattice in LDS, 2 lattice streamed from global memory, 3 generic
-   bit-by-bit kernel for L not among the compiled sizes, 4 as 0 with the random
-   words made by a second wave of the workgroup) and whether the sizes run
-   batched in one persistent launch (all sizes keep lattices in LDS).
-   mc_set_chains_per_block prefers kind 4 where it fits.
+   mc_set_chains_per_block: chains per workgroup (1..64, one chain per lane of
+   the workgroup's first wave) of one size.
+   mc_get_launch: chains per workgroup, kernel kind and whether the sizes run
+   batched in one persistent launch (all sizes keep lattices in LDS).  Kinds:
+     0  lattice and per-level thresholds in LDS, one wave
+     1  lattice in LDS, thresholds read from global memory, one wave
+     2  lattice rows streamed from global memory, one wave
+     3  generic bit-by-bit kernel for L not among the compiled sizes
+     4  as 0, random words made by three producer waves of the workgroup, two
+        sites decided per threshold read (L <= 64)
+     5  L = 128, 256: lattice rows streamed from global memory one word at a
+        time, per-bin thresholds in LDS, producer waves as in 4
+     6  as 5 with the per-bin thresholds read from global memory.
+   mc_set_chains_per_block prefers kinds 4 and 5 (then 6) where they fit.
    mc_autotune: times probe_sweeps sweeps of every size on copies of the chain
-   state for 16, 32 and 64 chains per workgroup, with and without the producer
-   wave, and keeps the fastest (chains_per_block_out: n_sizes values,
-   nullable).  The chains are not advanced.  Both setters fail with MC_ESTATE while graphs of the context
+   state for 16, 32 and 64 chains per workgroup, with the producer/consumer
+   kinds and with the one-wave kinds, and keeps the fastest
+   (chains_per_block_out: n_sizes values, nullable).  The chains are not
+   advanced.  Both setters fail with MC_ESTATE while graphs of the context
    exist. */
 mc_status mc_set_chains_per_block(mc_ctx *ctx, int32_t size_idx, int32_t chains_per_block);
 mc_status mc_get_launch(mc_ctx *ctx, int32_t size_idx, int32_t *chains_per_block, int32_t *kind, int32_t *batched);
