@@ -14,8 +14,9 @@ bounded sample of the same workload.
 
 Other workloads (--workload): recursion8 (L = 8, 16 chains, 10^4 sweeps, ten
 iterations from ln w = 0), batched (L = 16, 24, 32, 48, 64, 2048 chains each,
-graph-captured iterations), l128 (L = 128, 8192 chains), and copy (a plain
-device copy of known size, to calibrate the HBM byte counters).
+graph-captured iterations), l128 (L = 128, 8192 chains), thermo (the reduced
+reweighting of code (ii) at L = 256 for 4096 inverse temperatures), and copy (a
+plain device copy of known size, to calibrate the HBM byte counters).
 """
 import argparse
 import hashlib
@@ -48,7 +49,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="l32", choices=["l32", "recursion8", "batched", "l128", "copy"])
+    ap.add_argument("--workload", default="l32", choices=["l32", "recursion8", "batched", "l128", "thermo", "copy"])
     ap.add_argument("--chains", type=int, default=None)
     ap.add_argument("--sweeps", type=int, default=None)
     ap.add_argument("--iters", type=int, default=None)
@@ -257,6 +258,55 @@ def bench_l128(a, torch, mc):
     return res
 
 
+def bench_thermo(a, torch, mc):
+    """Reduced reweighting (mc_thermo, the paper's code (ii)) at L = 256:
+    E, C, F, S at n_beta inverse temperatures from a smooth synthetic weight of
+    32769 bins (65535 reachable levels)."""
+    L = 256
+    N = L * L
+    nb = (N >> 1) + 1
+    n_beta = a.chains or 4096
+    rng = np.random.default_rng(1)
+    x = (np.arange(nb) - nb / 2) / nb
+    w = -0.6 * N * x * x + np.cumsum(rng.normal(0, 0.05, nb))
+    betas = np.linspace(0.05, 2.0, n_beta)
+    ctx = mc.Context([(L, 2, 1, 1)])
+    ctx.init_weights(w)
+    for _ in range(a.warmup):
+        ctx.thermo(betas)
+    times = []
+    for _ in range(a.steps):
+        t0 = time.perf_counter()
+        ctx.thermo(betas)
+        times.append(time.perf_counter() - t0)
+    ctx.close()
+    dt = sum(times) / len(times)
+    terms = n_beta * (N - 1)
+    res = base_record(a, terms / dt, dt * 1e3,
+                      {"workload": "reduced reweighting at L=256: E, C, F, S at %d inverse temperatures from a "
+                                   "synthetic weight of 32769 bins" % n_beta, "L": L, "n_beta": n_beta},
+                      dtype="f64")
+    res["metric"] = "reweighting terms/s (inverse temperature x energy level)"
+    res["unit"] = "terms/s"
+    # per term, as the kernel evaluates it: two exponentials (about 12 fp64
+    # operations each; each term's is taken once for Z and the mean and once for
+    # the variance) and 10 additions and multiplications
+    flops = 34.0 * terms / dt
+    res["roofline"] = {"bound": "alu", "achieved": flops / 1e12, "peak": 78.6, "unit": "TFLOP/s",
+                       "frac": flops / 78.6e12, "traffic": None, "kernel": "k_thermo (mc_thermo, incl. copies)"}
+    if not a.no_cpu:
+        from oracle.thermo import thermo as o_thermo
+
+        sb = betas[:: 4]
+        t0 = time.perf_counter()
+        o_thermo(w, L, 1, sb)
+        tc = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": len(sb) * (N - 1) / tc, "unit": "terms/s", "cores": 1, "kind": "oracle",
+                               "sample": "%d of the inverse temperatures (%.2f s, numpy, single thread)"
+                                         % (len(sb), tc)}
+    return res
+
+
 def bench_copy(a, torch):
     """A plain device-to-device copy of known size (counter calibration)."""
     n = a.copy_bytes // 4
@@ -287,6 +337,8 @@ def main():
         res = bench_batched(a, torch, mc)
     elif a.workload == "l128":
         res = bench_l128(a, torch, mc)
+    elif a.workload == "thermo":
+        res = bench_thermo(a, torch, mc)
     else:
         res = bench_l32(a, torch, mc)
     print(json.dumps(res), flush=True)

@@ -149,6 +149,22 @@ mc_status mc_get_counters(mc_ctx *ctx, int32_t size_idx, int32_t *seam, uint32_t
 /* Read ln w of one size into host memory (n_bins values; synchronising). */
 mc_status mc_get_weights(mc_ctx *ctx, int32_t size_idx, double *lnW_host, int32_t n_bins);
 
+/* Reduced reweighting, the paper's code (ii) (Sec. 3.3, eq. reweighting2; the
+   quantities of Sec. 4.1): the thermodynamics of one size at n_beta inverse
+   temperatures (J = 1) from its current ln w alone.  The density of states is
+   taken inversely proportional to the weight of each reachable level's bin
+   (levels m = (E + 2N)/4 except 1 and N-1), normalised to count the 2^N
+   configurations.  beta_host: n_beta values, each positive and finite.
+   out_host: 4 * n_beta doubles; out[q * n_beta + k] is, at beta[k], for q = 0
+   the mean energy E = <H>, 1 the specific heat C = beta^2 (<H^2> - <H>^2),
+   2 the free energy F = -ln Z / beta, 3 the entropy S = beta (E - F), all
+   totals over the lattice.  Computed on the device in binary64 after the work
+   already queued on the context's stream; synchronising.  Host arrays are the
+   caller's.  MC_EINVAL for a null pointer, n_beta outside 1..2^20 or a beta
+   that is not positive and finite; MC_ENOMEM if the device buffer (5 * n_beta
+   doubles, kept by the context for later calls) cannot be allocated. */
+mc_status mc_thermo(mc_ctx *ctx, int32_t size_idx, const double *beta_host, int32_t n_beta, double *out_host);
+
 /* Progress of the weight recursion of one size (synchronising; each output may
    be NULL): updates done, first update (1-based) whose histogram was flat (0 =
    none yet), flatness of the last update, configurations kept by the joints

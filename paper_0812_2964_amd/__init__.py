@@ -25,7 +25,7 @@ EXPORTED = ["mc_create", "mc_destroy", "mc_n_bins", "mc_trace_elem_bytes", "mc_l
             "mc_get_weights", "mc_get_progress", "mc_set_chains_per_block", "mc_get_launch", "mc_autotune",
             "mc_graph_create", "mc_graph_launch", "mc_graph_destroy", "mc_sync", "mc_last_error",
             "mc_mlp_n_params", "mc_mlp_workspace_bytes", "mc_mlp_init", "mc_mlp_forward", "mc_mlp_loss_grad",
-            "mc_mlp_train", "mc_mlp_targets", "mc_mlp_predict_weights"]
+            "mc_mlp_train", "mc_mlp_targets", "mc_mlp_predict_weights", "mc_thermo"]
 
 
 class MCError(RuntimeError):
@@ -249,6 +249,16 @@ class Context:
         w = np.zeros(self.n_bins(i), dtype=np.float64)
         _check(lib().mc_get_weights(self._h, i, w.ctypes.data_as(ctypes.c_void_p), self.n_bins(i)))
         return w
+
+    def thermo(self, betas, i=0):
+        """E, C, F, S (totals) at the inverse temperatures `betas` from the
+        current ln w (mc_thermo); four float64 arrays."""
+        b = np.ascontiguousarray(np.asarray(betas, dtype=np.float64).ravel())
+        out = np.zeros(4 * b.size, dtype=np.float64)
+        _check(lib().mc_thermo(self._h, i, b.ctypes.data_as(ctypes.c_void_p), int(b.size),
+                               out.ctypes.data_as(ctypes.c_void_p)))
+        out = out.reshape(4, b.size)
+        return out[0], out[1], out[2], out[3]
 
     def progress(self, i=0):
         """(updates done, first flat update or 0, last update flat, kept before last update)"""

@@ -53,6 +53,8 @@ struct mc_ctx {
     int batch_grid = 0;
     size_t batch_lds = 0;
     int live_graphs = 0;  // graphs hold the tile buffer and the state pointers
+    double *thermo_buf = nullptr;  // mc_thermo: [thermo_cap] betas + [4 * thermo_cap] results
+    int thermo_cap = 0;
 };
 
 struct mc_graph {
@@ -281,6 +283,7 @@ mc_status mc_destroy(mc_ctx *ctx) {
     if (ctx->tiles_dev) (void)hipFree(ctx->tiles_dev);
     if (ctx->counter_dev) (void)hipFree(ctx->counter_dev);
     if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
+    if (ctx->thermo_buf) (void)hipFree(ctx->thermo_buf);
     delete ctx;
     return MC_OK;
 }
@@ -424,6 +427,34 @@ mc_status mc_get_weights(mc_ctx *ctx, int32_t i, double *lnW_host, int32_t n_bin
     const SizeDev &d = ctx->sizes[i].dev;
     if (!lnW_host || n_bins != d.n_bins) return fail(MC_EINVAL, "need %d bins", d.n_bins);
     HIP_OR_FAIL(ctx, hipMemcpyAsync(lnW_host, d.lnW, (size_t)d.n_bins * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+    return MC_OK;
+}
+
+mc_status mc_thermo(mc_ctx *ctx, int32_t i, const double *beta_host, int32_t n_beta, double *out_host) {
+    mc_status st = check_size(ctx, i);
+    if (st != MC_OK) return st;
+    if (!beta_host || !out_host) return fail(MC_EINVAL, "null pointer");
+    if (n_beta < 1 || n_beta > kThermoMaxBetas) return fail(MC_EINVAL, "n_beta must be 1..%d", kThermoMaxBetas);
+    for (int k = 0; k < n_beta; ++k)
+        if (!(beta_host[k] > 0.0) || !std::isfinite(beta_host[k]))
+            return fail(MC_EINVAL, "beta[%d] must be positive and finite", k);
+    if (n_beta > ctx->thermo_cap) {
+        HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+        if (ctx->thermo_buf) (void)hipFree(ctx->thermo_buf);
+        ctx->thermo_buf = nullptr;
+        ctx->thermo_cap = 0;
+        if (hipMalloc((void **)&ctx->thermo_buf, (size_t)5 * n_beta * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(MC_ENOMEM, "device allocation failed");
+        }
+        ctx->thermo_cap = n_beta;
+    }
+    double *beta_dev = ctx->thermo_buf, *out_dev = ctx->thermo_buf + n_beta;
+    const SizeDev &d = ctx->sizes[i].dev;
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(beta_dev, beta_host, (size_t)n_beta * 8, hipMemcpyHostToDevice, ctx->stream));
+    HIP_OR_FAIL(ctx, launch_thermo(d, beta_dev, n_beta, out_dev, ctx->stream));
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(out_host, out_dev, (size_t)4 * n_beta * 8, hipMemcpyDeviceToHost, ctx->stream));
     HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
     return MC_OK;
 }

@@ -77,6 +77,10 @@ hipError_t launch_advance(const SizeDev &s, int64_t M, hipStream_t st);
 hipError_t launch_join(const SizeDev &s, const void *trace, int64_t M, int32_t *cut, int32_t *hist, int mode,
                        hipStream_t st);
 hipError_t launch_update(const SizeDev &s, int32_t *hist, hipStream_t st);
+hipError_t launch_thermo(const SizeDev &s, const double *beta_dev, int n_beta, double *out_dev, hipStream_t st);
+
+// Most inverse temperatures one mc_thermo call takes.
+constexpr int kThermoMaxBetas = 1 << 20;
 
 // Message returned by mc_last_error() on this thread (mc_api.hip).
 void set_last_error(const char *msg);
