@@ -15,8 +15,10 @@ bounded sample of the same workload.
 Other workloads (--workload): recursion8 (L = 8, 16 chains, 10^4 sweeps, ten
 iterations from ln w = 0), batched (L = 16, 24, 32, 48, 64, 2048 chains each,
 graph-captured iterations), l128 (L = 128, 8192 chains), thermo (the reduced
-reweighting of code (ii) at L = 256 for 4096 inverse temperatures), and copy (a
-plain device copy of known size, to calibrate the HBM byte counters).
+reweighting of code (ii) at L = 256 for 4096 inverse temperatures), fig2 (the
+comparison of Fig. 2: detailed-balance joints against naive splices at L = 20,
+judged by code (ii) against the exact energy), and copy (a plain device copy of
+known size, to calibrate the HBM byte counters).
 """
 import argparse
 import hashlib
@@ -49,7 +51,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="l32", choices=["l32", "recursion8", "batched", "l128", "thermo", "copy"])
+    ap.add_argument("--workload", default="l32",
+                    choices=["l32", "recursion8", "batched", "l128", "thermo", "fig2", "copy"])
+    ap.add_argument("--rounds", type=int, default=None)
     ap.add_argument("--chains", type=int, default=None)
     ap.add_argument("--sweeps", type=int, default=None)
     ap.add_argument("--iters", type=int, default=None)
@@ -307,6 +311,66 @@ def bench_thermo(a, torch, mc):
     return res
 
 
+def bench_fig2(a, torch, mc):
+    """The comparison of Fig. 2 (Sec. 5): multicanonical weights generated with
+    detailed-balance joints (mode 0) and with naive splices (mode 1), then the
+    energy of code (ii) against Kaufman's exact energy of the L = 20 torus.
+    Each iteration collects about 10^8 attempts (M_total) in rounds of
+    32 chains x 100 sweeps (M_node), joined after every round (Algorithm
+    step 6), before the weight update; one bin per level, so that the energy
+    resolution of the weight is that of the model."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import exact_ising as X
+
+    L, P, M = 20, a.chains or 32, a.sweeps or 100
+    N = L * L
+    rounds = a.rounds or max(1, round(1e8 / (P * M * N)))
+    iters = a.iters or 200
+    betas = np.round(np.linspace(0.05, 1.0, 20), 4)
+    exact = np.array([X.mean_energy_exact(L, b) for b in betas])
+    res = base_record(a, 0.0, 0.0, {"workload": "Fig. 2 comparison: L=20, %d chains x %d sweeps per round, %d "
+                                                "rounds per iteration, %d iterations from ln w = 0, one bin per "
+                                                "level, seed 1" % (P, M, rounds, iters),
+                                    "L": L, "chains": P, "sweeps_per_round": M, "rounds_per_iteration": rounds,
+                                    "iterations": iters})
+    res["metric"] = METRIC
+    total_att, total_s = 0, 0.0
+    res["modes"] = {}
+    for mode in (0, 1):
+        ctx = mc.Context([(L, P, 1, 0)])
+        tr, h, cut = ctx.new_trace(M), ctx.new_hist(), ctx.new_cut()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        kept = 0
+        for it in range(iters):
+            for _ in range(rounds):
+                ctx.run_chains(M, tr, h)
+                ctx.join(tr, cut, h, mode)
+            ctx.update_weights(h, want=False)
+            if (it + 1) % 50 == 0:
+                torch.cuda.synchronize()
+                log("bench fig2: mode %d, iteration %d (%.1f s)" % (mode, it + 1, time.perf_counter() - t0))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        upd, first_flat, _, kept = ctx.progress()
+        e = ctx.thermo(betas)[0]
+        ctx.close()
+        dev = (e - exact) / N
+        hi = betas < 0.35
+        total_att += iters * rounds * P * M * N
+        total_s += dt
+        res["modes"]["detailed_balance" if mode == 0 else "naive"] = {
+            "first_flat_iteration": first_flat or None,
+            "kept_fraction_last_iteration": kept / float(rounds * P * M),
+            "max_abs_dE_per_site_beta_lt_0.35": float(np.max(np.abs(dev[hi]))),
+            "max_abs_dE_per_site_beta_ge_0.35": float(np.max(np.abs(dev[~hi]))),
+            "dE_per_site": {str(b): float(d) for b, d in zip(betas, dev)},
+            "seconds": dt}
+    res["value"] = total_att / total_s
+    res["ms_per_step"] = total_s / (2 * iters) * 1e3
+    return res
+
+
 def bench_copy(a, torch):
     """A plain device-to-device copy of known size (counter calibration)."""
     n = a.copy_bytes // 4
@@ -339,6 +403,8 @@ def main():
         res = bench_l128(a, torch, mc)
     elif a.workload == "thermo":
         res = bench_thermo(a, torch, mc)
+    elif a.workload == "fig2":
+        res = bench_fig2(a, torch, mc)
     else:
         res = bench_l32(a, torch, mc)
     print(json.dumps(res), flush=True)
