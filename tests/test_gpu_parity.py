@@ -290,3 +290,84 @@ def test_bench_workload_full_size_sampled():
             sigma = int(lv[i, M - 1])
     assert seam == sigma
     assert checked > 40
+
+
+def test_l128_workload_full_chain_count_sampled():
+    """L = 128 with the workload's 8192 chains in the default launch (the
+    streamed-row kernel with the per-bin table in LDS), a non-trivial weight
+    (at ln w = 0 every flip is accepted), four sweeps: sampled chains replayed
+    by the oracle bit for bit; histograms and cut points through properties
+    that hold at any size."""
+    mc = _mc()
+    L, P, M, N, bs = 128, 8192, 4, 128 * 128, 1
+    nb = (N >> bs) + 1
+    w = _smooth_weight(L, bs, 21)
+    ctx = mc.Context([(L, P, 1, bs)])
+    ctx.init_weights(w)
+    assert ctx.launch()[1] == 5
+    tr, h, cut = ctx.new_trace(M), ctx.new_hist(), ctx.new_cut()
+    ctx.run_chains(M, tr, h)
+    raw = _np(h).copy()
+    ctx.join(tr, cut, h)
+    joined = _np(h).copy()
+    levels = ctx.levels()
+    sampled = (0, 31, 32, 4095, 8191)
+    spins = {c: ctx.spins(c) for c in sampled}
+    trace = _np(tr)
+    cuts = _np(cut)
+    ctx.close()
+    for c in sampled:
+        s0 = O.init_chain(L, 1, c)
+        m0 = (O.energy(L, s0) + 2 * N) // 4
+        s, m, otr, _ = O.sweeps(L, 1, bs, c, s0, m0, 0, M, w)
+        assert np.array_equal(trace[c].astype(np.int32), otr), c
+        assert np.array_equal(spins[c], s) and levels[c] == m, c
+    lv = trace.astype(np.int64) + N // 2
+    assert raw.sum() == P * M
+    assert np.array_equal(raw, np.bincount((lv >> bs).ravel(), minlength=nb))
+    keep = np.arange(M)[None, :] >= np.where(cuts > 0, cuts - 1, M)[:, None]
+    assert np.array_equal(joined, np.bincount((lv[keep] >> bs), minlength=nb))
+    sigma = -1
+    for i in range(P):
+        c = cuts[i]
+        if sigma >= 0 and i % 61 == 0:
+            ws = w[sigma >> bs]
+            upto = (c - 1) if c > 0 else M
+            for k in range(upto + (1 if c > 0 else 0)):
+                acc = O.uniform(1, L, 2, 0, i, k) <= O.threshold(w[lv[i, k] >> bs] - ws)
+                assert acc == (c > 0 and k == c - 1), (i, k, c)
+        if c > 0:
+            sigma = int(lv[i, M - 1])
+
+
+def test_batched_workload_full_chain_count_sampled():
+    """The batched workload's sizes and chain counts (L = 16, 24, 32, 48, 64,
+    2048 chains each) in one persistent launch, with non-trivial weights:
+    sampled chains of every size replayed by the oracle, raw histograms equal
+    to the bincount of the traces."""
+    mc = _mc()
+    Ls, P, M, bs = [16, 24, 32, 48, 64], 2048, 12, 1
+    ws = [_smooth_weight(L, bs, 30 + L) for L in Ls]
+    ctx = mc.Context([(L, P, 1, bs) for L in Ls])
+    for i, w in enumerate(ws):
+        ctx.init_weights(w, i)
+    assert all(ctx.launch(i)[2] for i in range(len(Ls)))  # batched
+    trs = [ctx.new_trace(M, i) for i in range(len(Ls))]
+    hs = [ctx.new_hist(i) for i in range(len(Ls))]
+    ctx.run_chains(M, trs, hs)
+    sampled = (0, 63, 64, 1023, 2047)
+    res = []
+    for i, L in enumerate(Ls):
+        res.append((_np(trs[i]), _np(hs[i]).copy(), ctx.levels(i), {c: ctx.spins(c, i) for c in sampled}))
+    ctx.close()
+    for i, L in enumerate(Ls):
+        N = L * L
+        trace, raw, levels, spins = res[i]
+        for c in sampled:
+            s0 = O.init_chain(L, 1, c)
+            m0 = (O.energy(L, s0) + 2 * N) // 4
+            s, m, otr, _ = O.sweeps(L, 1, bs, c, s0, m0, 0, M, ws[i])
+            assert np.array_equal(trace[c].astype(np.int32), otr), (L, c)
+            assert np.array_equal(spins[c], s) and levels[c] == m, (L, c)
+        lv = trace.astype(np.int64) + N // 2
+        assert np.array_equal(raw, np.bincount((lv >> bs).ravel(), minlength=(N >> bs) + 1)), L
