@@ -17,8 +17,9 @@ iterations from ln w = 0), batched (L = 16, 24, 32, 48, 64, 2048 chains each,
 graph-captured iterations), l128 (L = 128, 8192 chains), thermo (the reduced
 reweighting of code (ii) at L = 256 for 4096 inverse temperatures), fig2 (the
 comparison of Fig. 2: detailed-balance joints against naive splices at L = 20,
-judged by code (ii) against the exact energy), and copy (a plain device copy of
-known size, to calibrate the HBM byte counters).
+judged by code (ii) against the exact energy), learned (iterations to flat at
+L = 64 from the network's proposal against ln w = 0), and copy (a plain device
+copy of known size, to calibrate the HBM byte counters).
 """
 import argparse
 import hashlib
@@ -52,7 +53,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="l32",
-                    choices=["l32", "recursion8", "batched", "l128", "thermo", "fig2", "copy"])
+                    choices=["l32", "recursion8", "batched", "l128", "thermo", "fig2", "learned", "copy"])
     ap.add_argument("--rounds", type=int, default=None)
     ap.add_argument("--chains", type=int, default=None)
     ap.add_argument("--sweeps", type=int, default=None)
@@ -371,6 +372,49 @@ def bench_fig2(a, torch, mc):
     return res
 
 
+def bench_learned(a, torch, mc):
+    """The learned initial weight: the network is trained on converged weights
+    of L = 8, 16 and 32, and proposes the weight of L = 64; iterations to the
+    first flat histogram from that proposal against the recursion from
+    ln w = 0 (w^(1) = 1), with the same chains, sweeps and seed."""
+    from paper_0812_2964_amd.learned import Initializer, run_to_flat
+
+    P, M = a.chains or 4096, a.sweeps or 2000
+    cap = a.iters or 500
+    target = 64
+    t0 = time.perf_counter()
+    ini = Initializer(seed=1)
+    train = {}
+    for L, c in [(8, 60), (16, 200), (32, 400)]:
+        w, flat, done = run_to_flat(L, P, M, c, extra=4,
+                                    progress=lambda d, L=L: log("bench learned: L=%d, %d iterations" % (L, d))
+                                    if d % 40 == 0 else None)
+        train[L] = flat
+        if flat is not None:
+            ini.add(L, w)
+    loss = ini.fit(steps=4000, lr=2e-3)
+    t_train = time.perf_counter() - t0
+    log("bench learned: trained (loss %.3g) in %.1f s" % (loss, t_train))
+    runs = {}
+    for name, lnW0 in [("learned", ini.predict(target)), ("plain", None)]:
+        t1 = time.perf_counter()
+        _, flat, done = run_to_flat(target, P, M, cap, lnW0=lnW0,
+                                    progress=lambda d, n=name: log("bench learned: L=%d %s, %d iterations"
+                                                                   % (target, n, d)) if d % 40 == 0 else None)
+        runs[name] = {"iterations_to_flat": flat, "iterations_run": done, "seconds": time.perf_counter() - t1}
+    att = sum(r["iterations_run"] for r in runs.values()) * P * M * target * target
+    sec = sum(r["seconds"] for r in runs.values())
+    res = base_record(a, att / sec, sec / max(1, sum(r["iterations_run"] for r in runs.values())) * 1e3,
+                      {"workload": "learned initial weight for L=%d: network trained on converged ln w of L=8, 16, 32 "
+                                   "(%d chains x %d sweeps per iteration, width-8 bins, seed 1), iterations to flat "
+                                   "against ln w = 0, cap %d" % (target, P, M, cap),
+                       "L": target, "chains": P, "sweeps_per_iter": M, "cap": cap})
+    res["training"] = {"first_flat": train, "loss": loss, "seconds": t_train}
+    res["iterations_to_flat"] = {k: v["iterations_to_flat"] for k, v in runs.items()}
+    res["runs"] = runs
+    return res
+
+
 def bench_copy(a, torch):
     """A plain device-to-device copy of known size (counter calibration)."""
     n = a.copy_bytes // 4
@@ -405,6 +449,8 @@ def main():
         res = bench_thermo(a, torch, mc)
     elif a.workload == "fig2":
         res = bench_fig2(a, torch, mc)
+    elif a.workload == "learned":
+        res = bench_learned(a, torch, mc)
     else:
         res = bench_l32(a, torch, mc)
     print(json.dumps(res), flush=True)

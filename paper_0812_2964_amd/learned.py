@@ -14,10 +14,11 @@ import numpy as np
 from . import Context, MLP, mlp_targets
 
 
-def run_to_flat(L, n_chains, n_sweeps, cap, lnW0=None, seed=1, bin_shift=1, extra=0, per_launch=4):
+def run_to_flat(L, n_chains, n_sweeps, cap, lnW0=None, seed=1, bin_shift=1, extra=0, per_launch=4, progress=None):
     """Recursion until the first flat histogram (then `extra` more
     iterations), at most `cap` iterations, replaying a captured graph of
-    `per_launch` iterations.  Returns (ln w, first flat iteration or None,
+    `per_launch` iterations.  progress(iterations done), if given, is called
+    after every replay.  Returns (ln w, first flat iteration or None,
     iterations run)."""
     ctx = Context([(L, n_chains, seed, bin_shift)])
     ctx.init_weights(lnW0)
@@ -28,6 +29,8 @@ def run_to_flat(L, n_chains, n_sweeps, cap, lnW0=None, seed=1, bin_shift=1, extr
         graph.launch()
         done += per_launch
         updates, first_flat, _, _ = ctx.progress()
+        if progress is not None:
+            progress(done)
         if first_flat and flat_at is None:
             flat_at = first_flat
         if flat_at is not None and updates >= flat_at + extra:
