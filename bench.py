@@ -17,7 +17,7 @@ iterations from ln w = 0), batched (L = 16, 24, 32, 48, 64, 2048 chains each,
 graph-captured iterations), l128 (L = 128, 8192 chains), thermo (the reduced
 reweighting of code (ii) at L = 256 for 4096 inverse temperatures), fig2 (the
 comparison of Fig. 2: detailed-balance joints against naive splices at L = 20,
-judged by code (ii) against the exact energy), learned (iterations to flat at
+measured by code (ii) against the exact energy), learned (iterations to flat at
 L = 64 from the network's proposal against ln w = 0), and copy (a plain device
 copy of known size, to calibrate the HBM byte counters).
 """
