@@ -113,7 +113,8 @@ def base_record(a, value, ms_per_step, config, dtype="u32"):
 
 def kernel_name(kind, L):
     return {0: "k_sweep_lds<%d,true>", 1: "k_sweep_lds<%d,false>", 2: "k_sweep_glb<%d>", 3: "k_sweep_generic",
-            4: "k_sweep_pc<%d>", 5: "k_sweep_big<%d,true>", 6: "k_sweep_big<%d,false>"}[kind].replace("%d", str(L))
+            4: "k_sweep_pc<%d>", 5: "k_sweep_big<%d,true>", 6: "k_sweep_big<%d,false>",
+            7: "k_sweep_pcq<%d>"}[kind].replace("%d", str(L))
 
 
 def roofline(attempts, kernel_s, traffic):
@@ -208,7 +209,7 @@ def bench_batched(a, torch, mc):
     sizes = [(L, P, 1, 1) for L in Ls]
     ctx = mc.Context(sizes)
     log("bench batched: autotuning")
-    cpbs = ctx.autotune(50)
+    cpbs = ctx.autotune(200)
     trs = [ctx.new_trace(M, i) for i in range(len(Ls))]
     hs = [ctx.new_hist(i) for i in range(len(Ls))]
     cuts = [ctx.new_cut(i) for i in range(len(Ls))]

@@ -186,11 +186,19 @@ mc_status mc_get_progress(mc_ctx *ctx, int32_t size_idx, int32_t *updates, int32
         sites decided per threshold read (L <= 64)
      5  L = 128, 256: lattice rows streamed from global memory one word at a
         time, per-bin thresholds in LDS, producer waves as in 4
-     6  as 5 with the per-bin thresholds read from global memory.
-   mc_set_chains_per_block prefers kinds 4 and 5 (then 6) where they fit.
+     6  as 5 with the per-bin thresholds read from global memory
+     7  as 4 with four lanes per chain: each step decides four sites, the
+        second pair under each of the four outcomes of the first
+        (8 <= L <= 64, at most 16 chains per workgroup).
+   By default 8 <= L <= 64 run kind 7 with 16 chains per workgroup and
+   L = 128, 256 kind 5 (else 6).  mc_set_chains_per_block picks kind 7 for
+   at most 16 chains per workgroup, else kind 4, where they fit.
    mc_autotune: times probe_sweeps sweeps of every size on copies of the chain
    state for 16, 32 and 64 chains per workgroup, with the producer/consumer
-   kinds and with the one-wave kinds, and keeps the fastest
+   kinds and with the one-wave kinds, and keeps the fastest; when the sizes
+   run batched it then times the batched launch itself for 16, 32 and 64
+   chains per workgroup everywhere and (up to six sizes) every mix of each
+   size's fastest plan and its widest one, and keeps the fastest
    (chains_per_block_out: n_sizes values, nullable).  The chains are not
    advanced.  Both setters fail with MC_ESTATE while graphs of the context
    exist. */

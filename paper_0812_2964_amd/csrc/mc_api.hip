@@ -102,9 +102,9 @@ void free_size(SizeDev &d) {
 
 // Default launch: for large lattices the streamed-row kernel with the per-bin
 // thresholds in LDS (32 chains per workgroup first), else with them in global
-// memory; otherwise the producer/consumer kernel with as many chains per
-// workgroup as fit in LDS, else the single-wave kernel with the thresholds in
-// LDS, else whatever fits.
+// memory; for 8 <= L <= 64 the quad-speculative kernel; otherwise the
+// producer/consumer kernel with as many chains per workgroup as fit in LDS,
+// else the single-wave kernel with the thresholds in LDS, else whatever fits.
 SizePlan default_plan(const SizeDev &d) {
     if (d.L >= 128) {
         const int order[4] = {32, 16, 64, 8};
@@ -114,6 +114,12 @@ SizePlan default_plan(const SizeDev &d) {
         }
         SizePlan q = plan_sweeps(d, 16, true);
         if (q.kind == kSweepBigGlb) return q;
+    }
+    if (d.L >= 8 && d.L <= 64) {
+        // the quad-speculative kernel at 16 chains per workgroup: fastest at
+        // every size measured (L = 16, 32, 64)
+        SizePlan q = plan_sweeps(d, 16, true);
+        if (q.kind == kSweepPCQ) return q;
     }
     for (int cpb = 64; cpb >= 8; cpb /= 2) {
         SizePlan q = plan_sweeps(d, cpb, true);
@@ -183,6 +189,124 @@ hipError_t enqueue_sweeps(mc_ctx *ctx, hipStream_t st, int64_t M, void *const *t
             e = launch_sweeps(ctx->sizes[i].dev, ctx->sizes[i].plan, M, trace[i], hist[i], st);
     }
     for (int i = 0; i < n && e == hipSuccess; ++i) e = launch_advance(ctx->sizes[i].dev, M, st);
+    return e;
+}
+
+// Copies of the chain state of every size and buffers for their traces, so
+// that probe launches leave the chains untouched.
+struct ScratchSizes {
+    std::vector<SizeDev> dev;
+    std::vector<void *> trace;
+    std::vector<int32_t *> hist;
+
+    hipError_t alloc(const mc_ctx *ctx, int64_t M) {
+        for (const auto &h : ctx->sizes) {
+            SizeDev d = h.dev;
+            d.lat = nullptr;
+            d.lev = nullptr;
+            d.ctl = nullptr;
+            void *tr = nullptr;
+            int32_t *hs = nullptr;
+            hipError_t e = hipMalloc((void **)&d.lat, (size_t)d.L * d.W * d.P * 4);
+            if (e == hipSuccess) e = hipMalloc((void **)&d.lev, (size_t)d.P * 4);
+            if (e == hipSuccess) e = hipMalloc((void **)&d.ctl, sizeof(Ctl));
+            if (e == hipSuccess) e = hipMalloc(&tr, (size_t)d.P * M * d.trace_bytes);
+            if (e == hipSuccess) e = hipMalloc((void **)&hs, (size_t)d.n_bins * 4);
+            dev.push_back(d);
+            trace.push_back(tr);
+            hist.push_back(hs);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    hipError_t refresh(const mc_ctx *ctx, hipStream_t st) {
+        for (size_t i = 0; i < dev.size(); ++i) {
+            const SizeDev &d = ctx->sizes[i].dev;
+            hipError_t e = hipMemcpyAsync(dev[i].lat, d.lat, (size_t)d.L * d.W * d.P * 4, hipMemcpyDeviceToDevice, st);
+            if (e == hipSuccess) e = hipMemcpyAsync(dev[i].lev, d.lev, (size_t)d.P * 4, hipMemcpyDeviceToDevice, st);
+            if (e == hipSuccess) e = hipMemcpyAsync(dev[i].ctl, d.ctl, sizeof(Ctl), hipMemcpyDeviceToDevice, st);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    ~ScratchSizes() {
+        for (size_t i = 0; i < dev.size(); ++i) {
+            if (dev[i].lat) (void)hipFree(dev[i].lat);
+            if (dev[i].lev) (void)hipFree(dev[i].lev);
+            if (dev[i].ctl) (void)hipFree(dev[i].ctl);
+            if (trace[i]) (void)hipFree(trace[i]);
+            if (hist[i]) (void)hipFree(hist[i]);
+        }
+    }
+};
+
+// Sizes that run batched share one persistent launch, whose time depends on
+// how many chains run at once as well as on each size's own speed.  Time the
+// batched launch for 16, 32 and 64 chains per workgroup everywhere and, with
+// at most six sizes, for every mix of each size's own best plan and its
+// widest one (most chains per workgroup); keep the fastest.
+hipError_t autotune_batched(mc_ctx *ctx, int64_t probe_sweeps, hipEvent_t e0, hipEvent_t e1) {
+    const int n = (int)ctx->sizes.size();
+    std::vector<SizePlan> own(n), wide(n), best(n);
+    for (int i = 0; i < n; ++i) {
+        own[i] = best[i] = ctx->sizes[i].plan;
+        wide[i] = own[i];
+        for (int cpb : {64, 32, 16}) {
+            const SizePlan q = plan_sweeps(ctx->sizes[i].dev, cpb, true);
+            if (batchable(q)) {
+                wide[i] = q;
+                break;
+            }
+        }
+    }
+    std::vector<std::vector<SizePlan>> cands;
+    for (int cpb : {16, 32, 64}) {
+        std::vector<SizePlan> c(n);
+        for (int i = 0; i < n; ++i) c[i] = plan_sweeps(ctx->sizes[i].dev, cpb, true);
+        cands.push_back(c);
+    }
+    if (n <= 6)
+        for (int mask = 0; mask < (1 << n); ++mask) {
+            std::vector<SizePlan> c(n);
+            for (int i = 0; i < n; ++i) c[i] = ((mask >> i) & 1) ? wide[i] : own[i];
+            cands.push_back(c);
+        }
+    else
+        cands.push_back(own);
+    ScratchSizes scr;
+    hipError_t e = scr.alloc(ctx, probe_sweeps);
+    float best_ms = 1e30f;
+    for (size_t k = 0; k < cands.size() && e == hipSuccess; ++k) {
+        bool ok = true;
+        for (int i = 0; i < n; ++i) {
+            ctx->sizes[i].plan = cands[k][i];
+            ok = ok && batchable(ctx->sizes[i].plan);
+        }
+        if (!ok) continue;
+        e = rebuild_launch(ctx);
+        if (e != hipSuccess || !ctx->batched) break;
+        std::vector<SizePlan> plans(n);
+        for (int i = 0; i < n; ++i) plans[i] = ctx->sizes[i].plan;
+        float t_min = 1e30f;
+        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+            e = scr.refresh(ctx, ctx->stream);
+            if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
+            if (e == hipSuccess)
+                e = launch_sweeps_batched(scr.dev.data(), plans.data(), n, ctx->tiles_dev, ctx->n_tiles,
+                                          ctx->counter_dev, ctx->batch_grid, ctx->batch_lds, probe_sweeps,
+                                          scr.trace.data(), scr.hist.data(), ctx->stream);
+            if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            t_min = std::min(t_min, ms);
+        }
+        if (e == hipSuccess && t_min < best_ms) {
+            best_ms = t_min;
+            best = plans;
+        }
+    }
+    for (int i = 0; i < n; ++i) ctx->sizes[i].plan = best[i];
     return e;
 }
 
@@ -552,10 +676,13 @@ mc_status mc_autotune(mc_ctx *ctx, int64_t probe_sweeps, int32_t *chains_per_blo
         if (e == hipSuccess) h.plan = best_plan;
         if (chains_per_block_out) chains_per_block_out[i] = h.plan.cpb;
     }
+    if (e == hipSuccess && ctx->sizes.size() > 1) e = autotune_batched(ctx, probe_sweeps, e0, e1);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (e != hipSuccess) return hip_fail(ctx, e, "autotune");
     HIP_OR_FAIL(ctx, rebuild_launch(ctx));
+    if (chains_per_block_out)
+        for (size_t i = 0; i < ctx->sizes.size(); ++i) chains_per_block_out[i] = ctx->sizes[i].plan.cpb;
     return MC_OK;
 }
 

@@ -44,6 +44,7 @@ enum SweepKind : int32_t {
     kSweepPC = 4,       // lattice and thresholds in LDS, random words from producer waves
     kSweepBig = 5,      // L >= 128: rows streamed from global memory, per-bin thresholds in LDS
     kSweepBigGlb = 6,   // the same with the per-bin thresholds read from global memory
+    kSweepPCQ = 7,      // as kSweepPC with four lanes per chain deciding four sites per step (8 <= L <= 64)
 };
 
 struct SizePlan {

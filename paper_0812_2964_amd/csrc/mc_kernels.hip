@@ -327,6 +327,16 @@ __device__ __forceinline__ uint4 lds_load128(uint32_t addr) {
     return make_uint4(v.x, v.y, v.z, v.w);
 }
 
+typedef uint32_t u32x3 __attribute__((ext_vector_type(3)));
+typedef __attribute__((address_space(3))) const u32x3 lds_u32x3;
+
+// Read the first 12 bytes of a 16-byte table entry (a narrower read, so that no
+// register of the result is dead while the read is in flight).
+__device__ __forceinline__ uint4 lds_load96(uint32_t addr) {
+    const u32x3 v = *(lds_u32x3 *)(size_t)addr;
+    return make_uint4(v.x, v.y, v.z, 0u);
+}
+
 // Signed byte k of w.
 __device__ __forceinline__ int32_t sbyte(uint32_t w, int k) { return (int32_t)(w << (24 - 8 * k)) >> 24; }
 
@@ -567,11 +577,214 @@ __device__ __forceinline__ void sweep_tile_pc(const SizeDev &s, int c0, int cpb,
 
 // 256 threads: one consumer wave and three producer waves.
 constexpr int kPcThreads = 256;
+// Chains per workgroup of the quad-speculative kernel (four lanes each).
+constexpr int kPcqMaxChains = 16;
 
 template <int L>
 __global__ __launch_bounds__(kPcThreads) void k_sweep_pc(PcParams p) {
     extern __shared__ uint32_t smem[];
     sweep_tile_pc<L>(p.s, blockIdx.x * p.cpb, p.cpb, p.R, p.M, p.trace, p.hist, smem);
+}
+
+// ---------------------------------------------------------------------------
+// Quad-speculative sweeps (8 <= L <= 64).  Each chain gets the four lanes of a
+// DPP quad.  Per step the quad decides four sites, pairs p and p+1: every lane
+// decides pair p from the chain's state and, at the same time, pair p+1 from
+// the state pair p would leave under one of its four outcomes (lane j assumes
+// site x accepted iff j & 1 and site x+1 accepted iff j & 2).  The six
+// thresholds do not depend on each other's outcome, and the lane whose
+// assumption was right hands its result to the quad.  Producer waves, tables
+// and buffers are those of the producer/consumer kernel.
+// ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ uint32_t quad_bcast(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
+}
+
+// One row of the quad consumer.  hxm, hym: all ones in lanes that assume site
+// x (x+1) of pair p accepted.
+template <int L>
+__device__ __forceinline__ void pcq_row(Row<L> &cur, const Row<L> &up, const Row<L> &dn, uint32_t &mib,
+                                        uint32_t pair_addr, const uint4 *urow, int cpb, uint32_t hxm, uint32_t hym) {
+    static_assert(L >= 8 && L % 4 == 0, "two pairs per step, site 0 decided before the last step");
+    constexpr int W = (L + 31) / 32;
+    constexpr int wl = (L - 1) >> 5, bl = (L - 1) & 31;
+    constexpr int NS = L / 4;  // steps of four sites
+    Row<L> xu, xd, hb, P0, P1, hs, fl;
+    const Row<L> nx = ring_next<L>(cur);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        xu.w[w] = cur.w[w] ^ up.w[w];
+        xd.w[w] = cur.w[w] ^ dn.w[w];
+        hb.w[w] = cur.w[w] ^ nx.w[w];
+        P0.w[w] = __builtin_amdgcn_bitop3_b32(xu.w[w], xd.w[w], hb.w[w], 0x96);  // parity
+        P1.w[w] = __builtin_amdgcn_bitop3_b32(xu.w[w], xd.w[w], hb.w[w], 0xE8);  // majority
+        fl.w[w] = 0u;
+    }
+#pragma unroll
+    for (int w = 0; w < W; ++w) hs.w[w] = (hb.w[w] << 1) | (w > 0 ? hb.w[w - 1] >> 31 : 0u);
+    hs.w[0] |= (hb.w[wl] >> bl) & 1u;
+    auto entry = [&](int p) {
+        const int w = (2 * p) >> 5, b = (2 * p) & 31;
+        const uint32_t idx =
+            ((P0.w[w] >> b) & 3u) | (((P1.w[w] >> b) & 3u) << 2) | (((hs.w[w] >> b) & 3u) << 4);
+        return lds_load96(pair_addr + idx * 16u);
+    };
+    bool aprev = false;
+    uint4 n0 = entry(0), n1 = entry(1);
+#pragma unroll
+    for (int st = 0; st < NS; ++st) {
+        const int p = 2 * st, x = 4 * st, w = x >> 5, b = x & 31;
+        if (st == 1) {
+            // the right neighbour of site L-1 is site 0, decided in the first step
+            const uint32_t hl = hb.w[wl] ^ ((fl.w[0] & 1u) << bl);
+            P0.w[wl] = __builtin_amdgcn_bitop3_b32(xu.w[wl], xd.w[wl], hl, 0x96);
+            P1.w[wl] = __builtin_amdgcn_bitop3_b32(xu.w[wl], xd.w[wl], hl, 0xE8);
+        }
+        const uint4 ea = n0;
+        // with two steps per row the last pair's entry is read after the fix above
+        const uint4 eb = (NS == 2 && st == 1) ? entry(3) : n1;
+        if (st + 1 < NS) {
+            n0 = entry(p + 2);
+            n1 = entry(p + 3);
+        }
+        const uint4 u4 = urow[st * cpb];
+        // pair p from the chain's state
+        const uint32_t V = aprev ? ea.z : ea.y;
+        // pair p+1 from the state left by the assumed outcome of pair p: the
+        // level move is byte 3 of V (both accepted), byte 3 of ea.x (only x+1),
+        // byte 2 of V (only x) or 0; selected with lane masks, without branches
+        const uint32_t ew = (V & hxm) | (ea.x & ~hxm);
+        const int32_t Eh = ((int32_t)(ew << (8u & ~hym)) >> 24) & (int32_t)(hxm | hym);
+        const uint32_t mh = mib + (uint32_t)Eh;
+        const uint32_t Vq = (eb.z & hym) | (eb.y & ~hym);
+        const uint32_t tx = lds_load(mib + sbyte(V, 0));
+        const uint32_t t0 = lds_load(mib + sbyte(ea.x, 0));
+        const uint32_t t1 = lds_load(mib + sbyte(V, 1));
+        const uint32_t qx = lds_load(mh + sbyte(Vq, 0));
+        const uint32_t q0 = lds_load(mh + sbyte(eb.x, 0));
+        const uint32_t q1 = lds_load(mh + sbyte(Vq, 1));
+        const bool bx = u4.z <= qx;
+        const uint32_t qn = bx ? q1 : q0;
+        const uint32_t nA = mh + (uint32_t)(bx ? sbyte(Vq, 3) : sbyte(eb.x, 3));
+        const uint32_t nB = mh + (uint32_t)(bx ? sbyte(Vq, 2) : 0);
+        const bool bx1 = u4.w <= qn;
+        // result of the assumption: next state, and the two decisions in bits 30, 31
+        const uint32_t res = (bx1 ? nA : nB) | (bx ? 1u << 30 : 0u) | (bx1 ? 1u << 31 : 0u);
+        const uint32_t r0 = quad_bcast<0x00>(res), r1 = quad_bcast<0x55>(res);
+        const uint32_t r2 = quad_bcast<0xAA>(res), r3 = quad_bcast<0xFF>(res);
+        const bool ax = u4.x <= tx;
+        const uint32_t tn = ax ? t1 : t0;
+        const uint32_t rA = ax ? r3 : r2, rB = ax ? r1 : r0;
+        const bool ax1 = u4.y <= tn;
+        const uint32_t sel = ax1 ? rA : rB;
+        mib = sel & 0x3FFFFFFFu;
+        fl.w[w] |= (ax ? 1u << b : 0u) | (ax1 ? 2u << b : 0u) | ((sel >> 30) << (b + 2));
+        aprev = (sel >> 31) != 0u;
+    }
+#pragma unroll
+    for (int w = 0; w < W; ++w) cur.w[w] ^= fl.w[w];
+}
+
+// Sweeps of chains c0 .. c0+cpb-1 (cpb <= 16); the chain of consumer lane l is
+// c0 + l/4.  Wave 0 consumes, waves 1.. produce.
+template <int L>
+__device__ __forceinline__ void sweep_tile_pcq(const SizeDev &s, int c0, int cpb, int R, int64_t M, void *trace,
+                                               int32_t *hist, uint32_t *smem) {
+    constexpr int W = (L + 31) / 32;
+    constexpr int N = L * L;
+    const PcLayout lay = pc_layout(L, W, N, s.n_bins, cpb, R);
+    char *lds = (char *)smem;
+    uint32_t *slat = (uint32_t *)(lds + lay.lat);
+    uint32_t *stab = (uint32_t *)(lds + lay.tab);
+    int32_t *shist = (int32_t *)(lds + lay.hist);
+    uint4 *ptbl = (uint4 *)(lds + lay.pair);
+    uint4 *ubuf = (uint4 *)(lds + lay.ubuf);
+    const int chunk_words = R * (L / 4) * cpb;  // uint4 per buffer
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int cl = lane >> 2, j = lane & 3;
+    const int c = c0 + cl;
+    const bool consumer = wave == 0;
+    const bool active = consumer && cl < cpb && c < s.P;
+    const bool lead = active && j == 0;  // one lane per chain for the global writes and atomics
+    const uint32_t hxm = 0u - (uint32_t)(j & 1), hym = 0u - (uint32_t)((j >> 1) & 1);
+    const uint32_t k0 = s.seed, k1 = (uint32_t)L;
+    const uint32_t g0 = s.ctl->g;
+    for (int i = threadIdx.x; i < (N + 1) * 5; i += blockDim.x) {
+        const int m = i / 5;
+        stab[i] = s.tab[(size_t)m * 8 + (i - 5 * m)];
+    }
+    for (int i = threadIdx.x; i < s.n_bins; i += blockDim.x) shist[i] = 0;
+    build_pair_table(ptbl, threadIdx.x, blockDim.x);
+    if (lead)
+        for (int w = 0; w < L * W; ++w) slat[w * cpb + cl] = s.lat[(size_t)w * s.P + c];
+    const int np = blockDim.x - 64, pt = threadIdx.x - 64;
+    const int per_sweep = L / R;
+    const int64_t n_chunks = M * per_sweep;
+    if (!consumer) pc_produce<L>(ubuf, R, 0u, g0, c0, cpb, k0, k1, pt, np);
+    __syncthreads();
+
+    uint32_t mib = 0;
+    Row<L> up, cur, dn;
+    const uint32_t tab_addr = (uint32_t)(size_t)(lds_u32 *)(stab);
+    const uint32_t pair_addr = (uint32_t)(size_t)(lds_u32 *)(ptbl);
+    if (active) mib = tab_addr + (uint32_t)kLevelBytes * (uint32_t)s.lev[c] + 16u;
+    for (int64_t i = 0; i < n_chunks; ++i) {
+        const int64_t k = i / per_sweep;
+        const int y0 = (int)(i - k * per_sweep) * R;
+        if (active) {
+            const uint4 *ub = ubuf + (size_t)(i & 1) * chunk_words;
+            auto load = [&](int y) {
+                Row<L> r;
+#pragma unroll
+                for (int w = 0; w < W; ++w) r.w[w] = slat[(y * W + w) * cpb + cl];
+                return r;
+            };
+            if (y0 == 0) {
+                up = load(L - 1);
+                cur = load(0);
+                dn = load(1);
+            }
+            for (int r = 0; r < R; ++r) {
+                const int y = y0 + r;
+                pcq_row<L>(cur, up, dn, mib, pair_addr, ub + (size_t)r * (L / 4) * cpb + cl, cpb, hxm, hym);
+                // the four lanes of the quad hold the same row
+#pragma unroll
+                for (int w = 0; w < W; ++w) slat[(y * W + w) * cpb + cl] = cur.w[w];
+                up = cur;
+                cur = dn;
+                dn = load(y + 2 < L ? y + 2 : y + 2 - L);
+            }
+            if (y0 + R == L && lead) {
+                const int m = (int)((mib - tab_addr - 16u) / (uint32_t)kLevelBytes);
+                const int ev = m - N / 2;
+                if (s.trace_bytes == 2)
+                    ((int16_t *)trace)[(size_t)c * M + k] = (int16_t)ev;
+                else
+                    ((int32_t *)trace)[(size_t)c * M + k] = ev;
+                atomicAdd(&shist[m >> s.bin_shift], 1);
+            }
+        } else if (!consumer && i + 1 < n_chunks) {
+            const int64_t k1s = (i + 1) / per_sweep;
+            const int y1 = (int)(i + 1 - k1s * per_sweep) * R;
+            pc_produce<L>(ubuf + (size_t)((i + 1) & 1) * chunk_words, R, (uint32_t)y1, g0 + (uint32_t)k1s, c0, cpb,
+                          k0, k1, pt, np);
+        }
+        __syncthreads();
+    }
+    if (lead) {
+        s.lev[c] = (int)((mib - tab_addr - 16u) / (uint32_t)kLevelBytes);
+        for (int w = 0; w < L * W; ++w) s.lat[(size_t)w * s.P + c] = slat[w * cpb + cl];
+    }
+    for (int i = threadIdx.x; i < s.n_bins; i += blockDim.x)
+        if (shist[i]) atomicAdd(&hist[i], shist[i]);
+    __syncthreads();
+}
+
+template <int L>
+__global__ __launch_bounds__(kPcThreads) void k_sweep_pcq(PcParams p) {
+    extern __shared__ uint32_t smem[];
+    sweep_tile_pcq<L>(p.s, blockIdx.x * p.cpb, p.cpb, p.R, p.M, p.trace, p.hist, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -898,6 +1111,18 @@ SizePlan plan_sweeps(const SizeDev &s, int cpb, bool allow_pc) {
             }
         }
     }
+    if (allow_pc && s.L >= 8 && s.L <= 64 && s.L % 4 == 0 && p.cpb <= kPcqMaxChains) {
+        for (int R = 8; R >= 1; R /= 2) {
+            if (s.L % R) continue;
+            const PcLayout lay = pc_layout(s.L, s.W, s.N, s.n_bins, p.cpb, R);
+            if (lay.total <= kLdsMax) {
+                p.kind = kSweepPCQ;
+                p.R = R;
+                p.lds_bytes = lay.total;
+                return p;
+            }
+        }
+    }
     if (allow_pc && s.L <= 64 && s.L % 4 == 0) {
         for (int R = 8; R >= 1; R /= 2) {
             if (s.L % R) continue;
@@ -926,7 +1151,9 @@ SizePlan plan_sweeps(const SizeDev &s, int cpb, bool allow_pc) {
     return p;
 }
 
-bool batchable(const SizePlan &p) { return p.kind == kSweepLdsTab || p.kind == kSweepLds || p.kind == kSweepPC; }
+bool batchable(const SizePlan &p) {
+    return p.kind == kSweepLdsTab || p.kind == kSweepLds || p.kind == kSweepPC || p.kind == kSweepPCQ;
+}
 
 // Raise a kernel's dynamic-LDS limit to at least `bytes` (never lower it: one
 // kernel can serve several sizes with different plans).
@@ -945,6 +1172,10 @@ static hipError_t prepare_L(const SizePlan &p) {
         if (p.kind == kSweepBigGlb)
             return allow_lds((const void *)k_sweep_big<L, false>, allowed_bigg, p.lds_bytes);
     }
+    if constexpr (L >= 8 && L <= 64 && L % 4 == 0) {
+        static size_t allowed_pcq = 0;
+        if (p.kind == kSweepPCQ) return allow_lds((const void *)k_sweep_pcq<L>, allowed_pcq, p.lds_bytes);
+    }
     if (p.kind == kSweepPC) return allow_lds((const void *)k_sweep_pc<L>, allowed_pc, p.lds_bytes);
     if (p.kind == kSweepLdsTab) return allow_lds((const void *)k_sweep_lds<L, true>, allowed_tab, p.lds_bytes);
     if (p.kind == kSweepLds) return allow_lds((const void *)k_sweep_lds<L, false>, allowed_notab, p.lds_bytes);
@@ -962,6 +1193,13 @@ static hipError_t launch_L(const SweepParams &p0, const SizePlan &pl, hipStream_
                 hipLaunchKernelGGL((k_sweep_big<L, true>), grid, dim3(kPcThreads), pl.lds_bytes, st, q);
             else
                 hipLaunchKernelGGL((k_sweep_big<L, false>), grid, dim3(kPcThreads), pl.lds_bytes, st, q);
+            return hipGetLastError();
+        }
+    }
+    if constexpr (L >= 8 && L <= 64 && L % 4 == 0) {
+        if (pl.kind == kSweepPCQ) {
+            PcParams q{p.s, p.M, p.trace, p.hist, pl.cpb, pl.R};
+            hipLaunchKernelGGL(k_sweep_pcq<L>, grid, dim3(kPcThreads), pl.lds_bytes, st, q);
             return hipGetLastError();
         }
     }
@@ -1041,6 +1279,12 @@ struct BatchParams {
 
 template <int L>
 __device__ __forceinline__ void batched_tile(const BatchParams &p, int si, int c0, uint32_t *smem) {
+    if constexpr (L >= 8) {
+        if (p.kind[si] == kSweepPCQ) {
+            sweep_tile_pcq<L>(p.sizes[si], c0, p.cpb[si], p.R[si], p.M, p.trace[si], p.hist[si], smem);
+            return;
+        }
+    }
     if (p.kind[si] == kSweepPC)
         sweep_tile_pc<L>(p.sizes[si], c0, p.cpb[si], p.R[si], p.M, p.trace[si], p.hist[si], smem);
     else if (p.kind[si] == kSweepLdsTab)

@@ -371,3 +371,26 @@ def test_batched_workload_full_chain_count_sampled():
             assert np.array_equal(spins[c], s) and levels[c] == m, (L, c)
         lv = trace.astype(np.int64) + N // 2
         assert np.array_equal(raw, np.bincount((lv >> bs).ravel(), minlength=(N >> bs) + 1)), L
+
+
+@pytest.mark.parametrize("cpb,kind", [(16, 7), (64, 4)])
+@pytest.mark.parametrize("L,P,bs,M", [(8, 37, 1, 20), (12, 20, 0, 12), (16, 33, 1, 10), (32, 70, 1, 4),
+                                      (48, 17, 1, 3), (64, 21, 1, 2)])
+def test_producer_consumer_kernels_bitexact(L, P, bs, M, cpb, kind):
+    """The quad-speculative kernel (kind 7: four lanes per chain, four sites per
+    step; 16 chains per workgroup, the default) and the pair kernel (kind 4:
+    one lane per chain, chosen with more chains per workgroup than kind 7
+    takes), against the oracle over two rounds with ragged workgroups."""
+    mc = _mc()
+    w = _smooth_weight(L, bs, 40 + L)
+    ctx = mc.Context([(L, P, 2, bs)])
+    ctx.init_weights(w)
+    ctx.set_chains_per_block(cpb)
+    assert ctx.launch()[1] == kind, ctx.launch()
+    R = O.Run(L, P, seed=2, bin_shift=bs, lnW=w)
+    for _ in range(2):
+        g = gpu_round(ctx, M)
+        o = oracle_round(R, M)
+        assert_round_equal(g, o)
+    assert_state_equal(ctx, R)
+    ctx.close()
