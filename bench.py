@@ -76,7 +76,7 @@ def kernel_source_hash():
 def traffic_from_profiles(L, P, M):
     """HBM bytes per sweep launch from the committed counter summary, if it was
     taken on the current kernel source and workload; else None."""
-    path = os.path.join(ROOT, "profiles", "k_sweep_pc_L32_4096x1e5_counters.md")
+    path = os.path.join(ROOT, "profiles", "k_sweep_pcq_L32_4096x1e5_counters.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
