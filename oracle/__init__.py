@@ -48,7 +48,8 @@ def lib():
     L.orc_level_reachable.restype = ctypes.c_int
     L.orc_tabulate.argtypes = [_i32, _i32, _p, _p]
     L.orc_sweeps.argtypes = [_i32, _u32, _i32, _u32, _p, _p, _u32, _i64, _p, _p, _p]
-    L.orc_join.argtypes = [_i32, _i32, _u32, _i32, _i64, _p, _p, _p, _u32, _i32, _p, _p, _p]
+    L.orc_join.argtypes = [_i32, _i32, _u32, _i32, _i64, _p, _p, _p, _u32, _i32, _p, _p, _p, _p]
+    L.orc_energy_order.argtypes = [_i32, _p, _p, _i32, _p]
     L.orc_update.argtypes = [_i32, _i32, _p, _p]
     L.orc_update.restype = ctypes.c_int
     L.orc_run_round.argtypes = [_i32, _u32, _i32, _u32, _i32, _i64, _u32, _p, _p, _p, _p, _p]
@@ -170,9 +171,21 @@ def sweeps(L, seed, bin_shift, c, spins, m, g0, M, lnW):
     return s, int(mm[0]), tr, h
 
 
+def energy_order(first, last, sigma):
+    """The energy ordering of the chains for one round (greedy chain of
+    nearest levels from the seam; see orc_energy_order).  first, last: levels
+    of each chain's first and last configuration."""
+    first = np.ascontiguousarray(first, dtype=np.int32)
+    last = np.ascontiguousarray(last, dtype=np.int32)
+    order = np.zeros(first.size, dtype=np.int32)
+    lib().orc_energy_order(first.size, _ptr(first), _ptr(last), sigma, _ptr(order))
+    return order
+
+
 def join(L, bin_shift, seed, trace, lnW, sigma, r, mode=0):
-    """Join one round.  trace: (p, M) array of E/4.  Returns
-    (cut, H, retained, new_sigma)."""
+    """Join one round.  trace: (p, M) array of E/4.  mode 0: detailed balance
+    in chain order; 1: naive splice; 2: detailed balance with the chains in
+    energy order.  Returns (cut, H, retained, new_sigma)."""
     tr = np.ascontiguousarray(trace, dtype=np.int32)
     p, M = tr.shape
     lnW = np.ascontiguousarray(lnW, dtype=np.float64)
@@ -180,8 +193,24 @@ def join(L, bin_shift, seed, trace, lnW, sigma, r, mode=0):
     cut = np.zeros(p, dtype=np.int32)
     H = np.zeros(n_bins(L, bin_shift), dtype=np.int64)
     ret = np.zeros(1, dtype=np.int64)
-    lib().orc_join(L, bin_shift, seed, p, M, _ptr(tr), _ptr(lnW), _ptr(sig), r, mode, _ptr(cut), _ptr(H), _ptr(ret))
+    order = None
+    if mode == 2:
+        half = L * L // 2
+        order = energy_order(tr[:, 0] + half, tr[:, M - 1] + half, sigma)
+    lib().orc_join(L, bin_shift, seed, p, M, _ptr(tr), _ptr(lnW), _ptr(sig), r, 1 if mode == 1 else 0,
+                   _ptr(order) if order is not None else None, _ptr(cut), _ptr(H), _ptr(ret))
     return cut, H, int(ret[0]), int(sig[0])
+
+
+def topup_sweeps(m_total, m_max, kept, swept):
+    """Sweeps of the next round of Algorithm step 6: the shortfall
+    m_total - kept at the rate kept / swept seen so far (kept configurations
+    per sweep of all chains), rounded up, within 1 .. m_max; m_max while
+    nothing has been kept.  Integers only."""
+    if kept <= 0:
+        return m_max
+    need = m_total - kept
+    return max(1, min(m_max, -(-need * swept // kept)))
 
 
 def update(L, bin_shift, H, lnW):
@@ -236,3 +265,24 @@ class Run:
         self.H[:] = 0
         self.retained = 0
         return flat
+
+    def iterate_topup(self, m_total, m_max, mode=0):
+        """One iteration with Algorithm step 6: rounds of m sweeps and joints
+        until the joined histogram holds at least m_total configurations,
+        then the weight update.  Returns (sweeps of each round, retained,
+        flat, traces of each round)."""
+        rounds, traces = [], []
+        kept0 = self.retained
+        swept = 0
+        while True:
+            m = topup_sweeps(m_total, m_max, self.retained - kept0, swept) if rounds else m_max
+            tr, _ = self.run(m)
+            self.join(tr, mode)
+            rounds.append(m)
+            traces.append(tr)
+            swept += m
+            if self.retained - kept0 >= m_total:
+                break
+        retained = self.retained
+        flat = self.update()
+        return rounds, retained, flat, traces

@@ -232,20 +232,25 @@ void orc_sweeps(int32_t L, uint32_t seed, int32_t bin_shift, uint32_t c, int8_t 
     *m_io = m;
 }
 
-/* Algorithm steps 3-5 for one round r over p chains in index order.
-   trace holds p rows of M values E/4.  *sigma_io is the seam level (-1 =
-   none).  cut[i] is the 1-based first kept position or -1.  Kept
-   configurations are added to H; their number to *retained.
+/* Algorithm steps 3-5 for one round r over p chains.  trace holds p rows of
+   M values E/4.  *sigma_io is the seam level (-1 = none).  cut[c] is the
+   1-based first kept position of chain c or -1.  Kept configurations are
+   added to H; their number to *retained.
+   order: NULL for the chains in index order, else the chain taken at each
+   position (a permutation of 0..p-1, the energy ordering of Sec. 2's remark;
+   see orc_energy_order).  The test of chain c's k-th configuration draws its
+   word from (round r, chain c, position k), whatever its place in the order.
    mode 0: detailed balance at the joints (the paper's method);
    mode 1: every chain kept whole (the naive splice compared in Sec. 5). */
 void orc_join(int32_t L, int32_t bin_shift, uint32_t seed, int32_t p, int64_t M, const int32_t *trace,
-              const double *lnW, int32_t *sigma_io, uint32_t r, int32_t mode, int32_t *cut, int64_t *H,
-              int64_t *retained)
+              const double *lnW, int32_t *sigma_io, uint32_t r, int32_t mode, const int32_t *order, int32_t *cut,
+              int64_t *H, int64_t *retained)
 {
     int N = L * L;
     int32_t sigma = *sigma_io;
-    for (int i = 0; i < p; ++i) {
-        const int32_t *tr = trace + (int64_t)i * M;
+    for (int t = 0; t < p; ++t) {
+        const int c = order ? order[t] : t;
+        const int32_t *tr = trace + (int64_t)c * M;
         int64_t kstar = -1;
         if (mode == 1 || sigma < 0) {
             kstar = 0;
@@ -253,7 +258,7 @@ void orc_join(int32_t L, int32_t bin_shift, uint32_t seed, int32_t p, int64_t M,
             for (int64_t k = 0; k < M; ++k) {
                 int32_t mk = tr[k] + N / 2;
                 double d = lnW[mk >> bin_shift] - lnW[sigma >> bin_shift];
-                uint32_t u = orc_uniform(seed, L, 2u, r, (uint32_t)i, (uint32_t)k);
+                uint32_t u = orc_uniform(seed, L, 2u, r, (uint32_t)c, (uint32_t)k);
                 if (orc_accept(orc_threshold(d), u)) {
                     kstar = k;
                     break;
@@ -264,12 +269,49 @@ void orc_join(int32_t L, int32_t bin_shift, uint32_t seed, int32_t p, int64_t M,
             for (int64_t k = kstar; k < M; ++k) H[(tr[k] + N / 2) >> bin_shift] += 1;
             *retained += M - kstar;
             sigma = tr[M - 1] + N / 2;
-            cut[i] = (int32_t)(kstar + 1);
+            cut[c] = (int32_t)(kstar + 1);
         } else {
-            cut[i] = -1;
+            cut[c] = -1;
         }
     }
     *sigma_io = sigma;
+}
+
+/* The energy ordering of the chains for one round (the paper suggests
+   ordering the nodes by the energies of their configurations to raise the
+   acceptance at the joints, Sec. 2, and leaves the rule open).  Reading: a
+   greedy chain of nearest levels.  first[c] and last[c] are the levels of
+   chain c's first and last configuration of the round.  Starting from the
+   seam sigma (or, with no seam, from chain 0 placed first), each position
+   takes the chain not yet placed whose first level is nearest to the last
+   level of the chain placed before it (or to the seam); ties go to the lower
+   level, then to the lower chain index.  O(p^2), for the test-suite. */
+void orc_energy_order(int32_t p, const int32_t *first, const int32_t *last, int32_t sigma, int32_t *order)
+{
+    char *used = (char *)calloc((size_t)p, 1);
+    int t = 0;
+    int32_t ref = sigma;
+    if (ref < 0 && p > 0) {
+        order[t++] = 0;
+        used[0] = 1;
+        ref = last[0];
+    }
+    for (; t < p; ++t) {
+        int best = -1;
+        for (int c = 0; c < p; ++c) {
+            if (used[c]) continue;
+            if (best < 0) {
+                best = c;
+                continue;
+            }
+            int dc = abs(first[c] - ref), db = abs(first[best] - ref);
+            if (dc < db || (dc == db && first[c] < first[best])) best = c;
+        }
+        order[t] = best;
+        used[best] = 1;
+        ref = last[best];
+    }
+    free(used);
 }
 
 /* Eq. (new_weight) in logarithms: ln w <- ln w - ln h where h > 0.
