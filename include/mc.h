@@ -122,7 +122,17 @@ mc_status mc_run_chains(mc_ctx *ctx, int64_t n_sweeps, void *const *trace_dev, i
                discarded configurations are removed from it, so on return it
                is the total histogram h(E) of the joined chain;
      mode:     0 = detailed balance (the paper's method), 1 = keep every
-               chain whole (the naive splice compared in Sec. 5).
+               chain whole (the naive splice compared in Sec. 5), 2 = detailed
+               balance with the chains taken in energy order (the ordering
+               Sec. 2 suggests to raise the acceptance at the joints, rule not
+               given there): starting from the seam (with none, chain 0
+               first), each position takes the chain not yet placed whose
+               first configuration's level is nearest to the level the chain
+               before it ended on, ties to the lower level, then the lower
+               index.  Mode 2 builds the order on the host from the trace's
+               first and last columns and synchronises.
+   The test of chain c's k-th configuration uses its own random word (round,
+   c, k) in every mode, whatever c's position.
    Errors: MC_EINVAL, MC_ESTATE (no matching mc_run_chains). */
 mc_status mc_join(mc_ctx *ctx, int32_t size_idx, const void *trace_dev, int64_t n_sweeps, int32_t *cut_dev,
                   int32_t *hist_dev, int32_t mode);
@@ -136,6 +146,28 @@ mc_status mc_join(mc_ctx *ctx, int32_t size_idx, const void *trace_dev, int64_t 
    Errors: MC_EINVAL. */
 mc_status mc_update_weights(mc_ctx *ctx, int32_t size_idx, int32_t *hist_dev, double *lnW_out_host,
                             int32_t *is_flat, int64_t *retained);
+
+/* One whole iteration with Algorithm step 6 (Sec. 2) for a context of one
+   size: rounds of mc_run_chains and mc_join (mode as there) until the joined
+   histogram holds at least m_total configurations, then the weight update of
+   mc_update_weights.  The first round makes m_max sweeps; each later one
+   ceil((m_total - kept) * swept / kept) sweeps within 1 .. m_max (the
+   shortfall at the rate kept so far, so that little more than m_total is
+   generated; m_max while nothing has been kept), and at most max_rounds
+   rounds are made.  Each round's histogram is added on the device to an
+   int64 histogram of the iteration, so the total may exceed 2^31.
+     trace_dev: device, room for [n_chains][m_max] trace entries (each round
+                writes [n_chains][m] there);
+     hist_dev:  device int32 [n_bins], zero on entry, zero on return;
+     cut_dev:   device int32 [n_chains], the cuts of the last round.
+   Host outputs (nullable): rounds made, sweeps per chain over all rounds,
+   configurations kept, flatness of the update.  Synchronises after each
+   round.  Errors: MC_EINVAL (not one size, bad argument), MC_EOVERFLOW
+   (n_chains * m_max >= 2^31), MC_ESTATE (a run or joint since the last
+   update), and those of the calls it makes. */
+mc_status mc_iterate_topup(mc_ctx *ctx, int64_t m_total, int64_t m_max, int32_t max_rounds, void *trace_dev,
+                           int32_t *hist_dev, int32_t *cut_dev, int32_t mode, int32_t *rounds_out, int64_t *sweeps_out,
+                           int64_t *retained_out, int32_t *is_flat);
 
 /* Inspection (synchronising, host outputs):
    levels_host [n_chains] current level m of each chain;

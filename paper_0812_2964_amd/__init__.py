@@ -25,7 +25,7 @@ EXPORTED = ["mc_create", "mc_destroy", "mc_n_bins", "mc_trace_elem_bytes", "mc_l
             "mc_get_weights", "mc_get_progress", "mc_set_chains_per_block", "mc_get_launch", "mc_autotune",
             "mc_graph_create", "mc_graph_launch", "mc_graph_destroy", "mc_sync", "mc_last_error",
             "mc_mlp_n_params", "mc_mlp_workspace_bytes", "mc_mlp_init", "mc_mlp_forward", "mc_mlp_loss_grad",
-            "mc_mlp_train", "mc_mlp_targets", "mc_mlp_predict_weights", "mc_thermo"]
+            "mc_mlp_train", "mc_mlp_targets", "mc_mlp_predict_weights", "mc_thermo", "mc_iterate_topup"]
 
 
 class MCError(RuntimeError):
@@ -63,6 +63,7 @@ def lib():
     L.mc_run_chains.argtypes = [p, i64, p, p]
     L.mc_join.argtypes = [p, i32, p, i64, p, p, i32]
     L.mc_update_weights.argtypes = [p, i32, p, p, p, p]
+    L.mc_iterate_topup.argtypes = [p, i64, i64, i32, p, p, p, i32, p, p, p, p]
     L.mc_get_levels.argtypes = [p, i32, p]
     L.mc_get_lattice.argtypes = [p, i32, i32, p, i32]
     L.mc_get_counters.argtypes = [p, i32, p, p, p]
@@ -216,6 +217,21 @@ class Context:
         _check(lib().mc_update_weights(self._h, i, hp, w.ctypes.data_as(ctypes.c_void_p), ctypes.byref(flat),
                                        ctypes.byref(ret)))
         return w, bool(flat.value), int(ret.value)
+
+    def iterate_topup(self, m_total, m_max, trace, hist, cut, mode=0, max_rounds=1000):
+        """One iteration with Algorithm step 6 (one-size contexts).  trace has
+        room for n_chains * m_max entries.  Returns (rounds, sweeps per chain,
+        configurations kept, flat flag)."""
+        import torch
+
+        P = self.sizes[0][1]
+        rounds, sweeps, kept, flat = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        _check(lib().mc_iterate_topup(self._h, int(m_total), int(m_max), int(max_rounds),
+                                      _dev_ptr(trace, self.trace_dtype(0), P * int(m_max), "trace"),
+                                      _dev_ptr(hist, torch.int32, self.n_bins(0), "hist"),
+                                      _dev_ptr(cut, torch.int32, P, "cut"), int(mode), ctypes.byref(rounds),
+                                      ctypes.byref(sweeps), ctypes.byref(kept), ctypes.byref(flat)))
+        return rounds.value, sweeps.value, kept.value, bool(flat.value)
 
     # -- inspection -------------------------------------------------------
     def levels(self, i=0):

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -97,6 +98,8 @@ void free_size(SizeDev &d) {
     if (d.tabc) (void)hipFree(d.tabc);
     if (d.ctl) (void)hipFree(d.ctl);
     if (d.scratch_cut) (void)hipFree(d.scratch_cut);
+    if (d.join_order) (void)hipFree(d.join_order);
+    if (d.hist64) (void)hipFree(d.hist64);
     d = SizeDev{};
 }
 
@@ -312,6 +315,62 @@ hipError_t autotune_batched(mc_ctx *ctx, int64_t probe_sweeps, hipEvent_t e0, hi
 
 }  // namespace
 
+// The energy ordering of the chains for one joint (the paper suggests ordering
+// the nodes by the energies of their configurations, Sec. 2, and leaves the
+// rule open): a greedy chain of nearest levels.  Starting from the seam (with
+// none, chain 0 goes first), each position takes the chain not yet placed
+// whose first level is nearest to the last level of the chain before it,
+// ties to the lower level, then the lower index.  O(P log P).
+static void energy_order(int P, const std::vector<int> &first, const std::vector<int> &last, int sigma,
+                         std::vector<int32_t> &order) {
+    std::set<std::pair<int, int>> left;
+    for (int c = 0; c < P; ++c) left.insert({first[c], c});
+    order.assign((size_t)P, 0);
+    int t = 0, ref = sigma;
+    if (ref < 0 && P > 0) {
+        order[t++] = 0;
+        left.erase({first[0], 0});
+        ref = last[0];
+    }
+    for (; t < P; ++t) {
+        auto up = left.lower_bound({ref, -1});  // nearest level >= ref, lowest index
+        auto pick = up;
+        if (up != left.begin()) {
+            const int below = std::prev(up)->first;
+            auto lo = left.lower_bound({below, -1});  // level below ref, lowest index
+            if (up == left.end() || ref - below <= up->first - ref) pick = lo;
+        }
+        order[t] = pick->second;
+        ref = last[pick->second];
+        left.erase(pick);
+    }
+}
+
+// The first and last levels of every chain's trace of one round (synchronising).
+static hipError_t trace_ends(mc_ctx *ctx, const SizeDev &d, const void *trace_dev, int64_t M, std::vector<int> &first,
+                             std::vector<int> &last) {
+    const size_t eb = (size_t)d.trace_bytes;
+    std::vector<char> a((size_t)d.P * eb), b((size_t)d.P * eb);
+    const char *t = (const char *)trace_dev;
+    hipError_t e = hipMemcpy2DAsync(a.data(), eb, t, (size_t)M * eb, eb, (size_t)d.P, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpy2DAsync(b.data(), eb, t + (size_t)(M - 1) * eb, (size_t)M * eb, eb, (size_t)d.P,
+                             hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return e;
+    first.resize((size_t)d.P);
+    last.resize((size_t)d.P);
+    auto level = [&](const char *q) {
+        const int v = eb == 2 ? (int)*(const int16_t *)q : (int)*(const int32_t *)q;
+        return std::min(std::max(v + d.N / 2, 0), d.N);
+    };
+    for (int c = 0; c < d.P; ++c) {
+        first[c] = level(a.data() + (size_t)c * eb);
+        last[c] = level(b.data() + (size_t)c * eb);
+    }
+    return hipSuccess;
+}
+
 void mcgpu::set_last_error(const char *msg) { g_err = msg; }
 
 extern "C" {
@@ -367,7 +426,9 @@ mc_status mc_create(const mc_size *sizes, int32_t n_sizes, void *hip_stream, mc_
             hipMalloc((void **)&d.tab, (size_t)(d.N + 1) * 8 * 4) != hipSuccess ||
             hipMalloc((void **)&d.tabc, (size_t)d.n_bins * (2 * d.tab_r + 1) * 4) != hipSuccess ||
             hipMalloc((void **)&d.ctl, sizeof(Ctl)) != hipSuccess ||
-            hipMalloc((void **)&d.scratch_cut, (size_t)d.P * 4) != hipSuccess) {
+            hipMalloc((void **)&d.scratch_cut, (size_t)d.P * 4) != hipSuccess ||
+            hipMalloc((void **)&d.join_order, (size_t)d.P * 4) != hipSuccess ||
+            hipMalloc((void **)&d.hist64, (size_t)d.n_bins * 8) != hipSuccess) {
             (void)hipGetLastError();
             st = fail(MC_ENOMEM, "device allocation failed for size %d", i);
             break;
@@ -378,6 +439,7 @@ mc_status mc_create(const mc_size *sizes, int32_t n_sizes, void *hip_stream, mc_
         hipError_t e = hipMemcpyAsync(d.ctl, &c0, sizeof c0, hipMemcpyHostToDevice, ctx->stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(d.lnW, zeros.data(), zeros.size() * 8, hipMemcpyHostToDevice, ctx->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(d.hist64, 0, (size_t)d.n_bins * 8, ctx->stream);
         if (e == hipSuccess) e = launch_init(d, ctx->stream);
         if (e == hipSuccess) e = launch_tabulate(d, ctx->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
@@ -473,11 +535,26 @@ mc_status mc_join(mc_ctx *ctx, int32_t i, const void *trace_dev, int64_t n_sweep
     if (st != MC_OK) return st;
     HostSize &h = ctx->sizes[i];
     if (!trace_dev || !cut_dev || !hist_dev) return fail(MC_EINVAL, "null trace, cut or hist");
-    if (mode != 0 && mode != 1) return fail(MC_EINVAL, "mode must be 0 or 1");
+    if (mode < 0 || mode > 2) return fail(MC_EINVAL, "mode must be 0, 1 or 2");
     if (h.last_M == 0) return fail(MC_ESTATE, "size %d: no mc_run_chains to join", i);
     if (n_sweeps != h.last_M)
         return fail(MC_EINVAL, "n_sweeps=%lld differs from the last run (%lld)", (long long)n_sweeps, (long long)h.last_M);
-    HIP_OR_FAIL(ctx, launch_join(h.dev, trace_dev, n_sweeps, cut_dev, hist_dev, mode, ctx->stream));
+    const int32_t *order = nullptr;
+    if (mode == 2) {
+        std::vector<int> first, last;
+        HIP_OR_FAIL(ctx, trace_ends(ctx, h.dev, trace_dev, n_sweeps, first, last));
+        Ctl c{};
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(&c, h.dev.ctl, sizeof c, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+        std::vector<int32_t> ord;
+        energy_order(h.dev.P, first, last, c.sigma, ord);
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(h.dev.join_order, ord.data(), ord.size() * 4, hipMemcpyHostToDevice,
+                                        ctx->stream));
+        HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+        order = h.dev.join_order;
+    }
+    HIP_OR_FAIL(ctx, launch_join(h.dev, trace_dev, n_sweeps, cut_dev, hist_dev, mode == 2 ? 0 : mode, order,
+                                 ctx->stream));
     h.last_M = 0;
     return MC_OK;
 }
@@ -500,6 +577,63 @@ mc_status mc_update_weights(mc_ctx *ctx, int32_t i, int32_t *hist_dev, double *l
         if (is_flat) *is_flat = c.flat;
         if (retained) *retained = c.retained_last;
     }
+    return MC_OK;
+}
+
+mc_status mc_iterate_topup(mc_ctx *ctx, int64_t m_total, int64_t m_max, int32_t max_rounds, void *trace_dev,
+                           int32_t *hist_dev, int32_t *cut_dev, int32_t mode, int32_t *rounds_out, int64_t *sweeps_out,
+                           int64_t *retained_out, int32_t *is_flat) {
+    mc_status st = check_ctx(ctx);
+    if (st != MC_OK) return st;
+    if (ctx->sizes.size() != 1) return fail(MC_EINVAL, "mc_iterate_topup needs a context of one size");
+    HostSize &h = ctx->sizes[0];
+    const SizeDev &d = h.dev;
+    if (!trace_dev || !hist_dev || !cut_dev) return fail(MC_EINVAL, "null trace, hist or cut");
+    if (m_total < 1) return fail(MC_EINVAL, "m_total must be positive");
+    if (m_max < 1 || m_max > 0x7FFFFFFF) return fail(MC_EINVAL, "m_max must be 1..2^31-1");
+    if (max_rounds < 1 || max_rounds > 1000000) return fail(MC_EINVAL, "max_rounds must be 1..10^6");
+    if (mode < 0 || mode > 2) return fail(MC_EINVAL, "mode must be 0, 1 or 2");
+    if ((int64_t)d.P * m_max > 0x7FFFFFFFll)
+        return fail(MC_EOVERFLOW, "%d chains x %lld sweeps exceed the int32 histogram of one round", d.P,
+                    (long long)m_max);
+    if (h.pending != 0 || h.last_M != 0)
+        return fail(MC_ESTATE, "mc_iterate_topup must start after a weight update");
+    Ctl c{};
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(&c, d.ctl, sizeof c, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+    const int64_t kept0 = c.retained;
+    int64_t kept = 0, swept = 0;
+    int rounds = 0;
+    for (;;) {
+        // Algorithm step 6: the next round covers the shortfall at the rate seen so far
+        int64_t m = m_max;
+        if (rounds > 0 && kept > 0) {
+            const int64_t need = m_total - kept;
+            const __int128 q = ((__int128)need * swept + kept - 1) / kept;
+            m = q > m_max ? m_max : std::max<int64_t>(1, (int64_t)q);
+        }
+        void *tr[1] = {trace_dev};
+        int32_t *hs[1] = {hist_dev};
+        st = mc_run_chains(ctx, m, tr, hs);
+        if (st != MC_OK) return st;
+        st = mc_join(ctx, 0, trace_dev, m, cut_dev, hist_dev, mode);
+        if (st != MC_OK) return st;
+        HIP_OR_FAIL(ctx, launch_fold_hist(d, hist_dev, ctx->stream));
+        h.pending = 0;
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(&c, d.ctl, sizeof c, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+        kept = c.retained - kept0;
+        swept += m;
+        rounds += 1;
+        if (kept >= m_total || rounds >= max_rounds) break;
+    }
+    HIP_OR_FAIL(ctx, launch_update64(d, ctx->stream));
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(&c, d.ctl, sizeof c, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+    if (rounds_out) *rounds_out = rounds;
+    if (sweeps_out) *sweeps_out = swept;
+    if (retained_out) *retained_out = c.retained_last;
+    if (is_flat) *is_flat = c.flat;
     return MC_OK;
 }
 
@@ -714,7 +848,7 @@ mc_status mc_graph_create(mc_ctx *ctx, int64_t n_sweeps, int32_t n_iters, void *
     for (int it = 0; it < n_iters && e == hipSuccess; ++it) {
         e = enqueue_sweeps(ctx, cs, n_sweeps, trace_dev, hist_dev);
         for (int i = 0; i < n && e == hipSuccess; ++i)
-            e = launch_join(ctx->sizes[i].dev, trace_dev[i], n_sweeps, cut_dev[i], hist_dev[i], mode, cs);
+            e = launch_join(ctx->sizes[i].dev, trace_dev[i], n_sweeps, cut_dev[i], hist_dev[i], mode, nullptr, cs);
         for (int i = 0; i < n && e == hipSuccess; ++i) e = launch_update(ctx->sizes[i].dev, hist_dev[i], cs);
     }
     hipGraph_t graph = nullptr;

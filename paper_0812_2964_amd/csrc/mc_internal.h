@@ -33,6 +33,8 @@ struct SizeDev {
     int32_t tab_r;          // 2 with one level per bin, else 1
     Ctl *ctl;
     int32_t *scratch_cut;   // [P] speculative cut points of the joint
+    int32_t *join_order;    // [P] chain at each position of an energy-ordered joint
+    int64_t *hist64;        // [n_bins] joined histogram of Algorithm step 6's rounds
 };
 
 // How the sweeps of one size are launched.
@@ -75,9 +77,14 @@ hipError_t launch_sweeps_batched(const SizeDev *sizes, const SizePlan *plans, in
                                  int n_tiles, int32_t *counter_dev, int grid, size_t lds_bytes, int64_t M,
                                  void *const *trace, int32_t *const *hist, hipStream_t st);
 hipError_t launch_advance(const SizeDev &s, int64_t M, hipStream_t st);
+// order: the chain at each position of the joint, or nullptr for index order.
 hipError_t launch_join(const SizeDev &s, const void *trace, int64_t M, int32_t *cut, int32_t *hist, int mode,
-                       hipStream_t st);
+                       const int32_t *order, hipStream_t st);
 hipError_t launch_update(const SizeDev &s, int32_t *hist, hipStream_t st);
+// Add a round's int32 histogram to s.hist64 and clear it; the update from
+// s.hist64 (which it then clears).
+hipError_t launch_fold_hist(const SizeDev &s, int32_t *hist, hipStream_t st);
+hipError_t launch_update64(const SizeDev &s, hipStream_t st);
 hipError_t launch_thermo(const SizeDev &s, const double *beta_dev, int n_beta, double *out_dev, hipStream_t st);
 
 // Most inverse temperatures one mc_thermo call takes.

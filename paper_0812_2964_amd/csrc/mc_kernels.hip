@@ -1362,6 +1362,9 @@ hipError_t launch_sweeps_batched(const SizeDev *sizes, const SizePlan *plans, in
 //      speculated one (the test depends on the seam only through ln w of its
 //      bin, and its random words do not depend on the seam at all).
 //  (3) k_join_hist: the discarded prefixes are taken out of the histogram.
+// "In order" means by position t = 0 .. P-1; the chain at position t is
+// order[t] (the energy ordering of the chains, Sec. 2), or t without an order.
+// A chain's tests draw their words from its own index, whatever its position.
 // ---------------------------------------------------------------------------
 struct JoinParams {
     SizeDev s;
@@ -1370,7 +1373,10 @@ struct JoinParams {
     int32_t *cut;
     int32_t *hist;
     int32_t mode;
+    const int32_t *order;  // nullptr: index order
 };
+
+__device__ __forceinline__ int join_chain(const JoinParams &p, int t) { return p.order ? p.order[t] : t; }
 
 template <typename TT>
 __device__ int join_scan(const SizeDev &s, const TT *row, int64_t M, int sigma, uint32_t r, uint32_t i) {
@@ -1395,17 +1401,18 @@ __device__ int join_scan(const SizeDev &s, const TT *row, int64_t M, int sigma, 
 template <typename TT>
 __global__ __launch_bounds__(64) void k_join_spec(JoinParams p) {
     const SizeDev &s = p.s;
-    const int i = blockIdx.x;
+    const int t = blockIdx.x;  // position
+    const int i = join_chain(p, t);
     const TT *tr = (const TT *)p.trace;
     const int half = s.N / 2;
-    const int sigma =
-        (i == 0) ? s.ctl->sigma : min(max((int)tr[(size_t)(i - 1) * p.M + (p.M - 1)] + half, 0), s.N);
+    const int sigma = (t == 0) ? s.ctl->sigma
+                               : min(max((int)tr[(size_t)join_chain(p, t - 1) * p.M + (p.M - 1)] + half, 0), s.N);
     int cut;
     if (p.mode == 1 || sigma < 0)
         cut = 1;
     else
         cut = join_scan<TT>(s, tr + (size_t)i * p.M, p.M, sigma, s.ctl->r, (uint32_t)i);
-    if (threadIdx.x == 0) s.scratch_cut[i] = cut;
+    if (threadIdx.x == 0) s.scratch_cut[t] = cut;
 }
 
 template <typename TT>
@@ -1425,16 +1432,18 @@ __global__ __launch_bounds__(64) void k_join_fix(JoinParams p) {
         __syncthreads();
         for (int t = lane; t < n; t += 64) {
             s_cut[t] = s.scratch_cut[c0 + t];
-            s_last[t + 1] = min(max((int)tr[(size_t)(c0 + t) * p.M + (p.M - 1)] + half, 0), s.N);
+            s_last[t + 1] = min(max((int)tr[(size_t)join_chain(p, c0 + t) * p.M + (p.M - 1)] + half, 0), s.N);
         }
         if (lane == 0)
-            s_last[0] = c0 > 0 ? min(max((int)tr[(size_t)(c0 - 1) * p.M + (p.M - 1)] + half, 0), s.N) : s.ctl->sigma;
+            s_last[0] = c0 > 0 ? min(max((int)tr[(size_t)join_chain(p, c0 - 1) * p.M + (p.M - 1)] + half, 0), s.N)
+                               : s.ctl->sigma;
         __syncthreads();
         for (int t = 0; t < n; ++t) {
-            const int i = c0 + t;
+            const int pos = c0 + t;
+            const int i = join_chain(p, pos);
             int cut = s_cut[t];
             const int spec = s_last[t];  // seam assumed by k_join_spec
-            if (p.mode == 0 && i > 0 && sigma >= 0 && (sigma >> s.bin_shift) != (spec >> s.bin_shift))
+            if (p.mode == 0 && pos > 0 && sigma >= 0 && (sigma >> s.bin_shift) != (spec >> s.bin_shift))
                 cut = join_scan<TT>(s, tr + (size_t)i * p.M, p.M, sigma, r, (uint32_t)i);
             if (lane == 0) p.cut[i] = cut;
             if (cut > 0) {
@@ -1491,8 +1500,8 @@ static hipError_t launch_join_T(const JoinParams &p, hipStream_t st) {
 }
 
 hipError_t launch_join(const SizeDev &s, const void *trace, int64_t M, int32_t *cut, int32_t *hist, int mode,
-                       hipStream_t st) {
-    JoinParams p{s, trace, M, cut, hist, mode};
+                       const int32_t *order, hipStream_t st) {
+    JoinParams p{s, trace, M, cut, hist, mode, order};
     return s.trace_bytes == 2 ? launch_join_T<int16_t>(p, st) : launch_join_T<int32_t>(p, st);
 }
 
@@ -1506,13 +1515,14 @@ __device__ __forceinline__ bool bin_reachable(int b, int bin_shift, int N) {
     return false;
 }
 
-__global__ __launch_bounds__(1024) void k_update(SizeDev s, int32_t *hist) {
+template <typename HT>
+__global__ __launch_bounds__(1024) void k_update(SizeDev s, HT *hist) {
     __shared__ long long s_min[16], s_sum[16];
     __shared__ int s_n[16];
     long long mn = 0x7FFFFFFFFFFFFFFFll, sum = 0;
     int n = 0;
     for (int b = threadIdx.x; b < s.n_bins; b += blockDim.x) {
-        const int h = hist[b];
+        const long long h = hist[b];
         if (h > 0) s.lnW[b] = s.lnW[b] - det_log((int64_t)h);
         if (bin_reachable(b, s.bin_shift, s.N)) {
             n += 1;
@@ -1554,7 +1564,29 @@ __global__ __launch_bounds__(1024) void k_update(SizeDev s, int32_t *hist) {
 }
 
 hipError_t launch_update(const SizeDev &s, int32_t *hist, hipStream_t st) {
-    hipLaunchKernelGGL(k_update, dim3(1), dim3(1024), 0, st, s, hist);
+    hipLaunchKernelGGL(k_update<int32_t>, dim3(1), dim3(1024), 0, st, s, hist);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_tabulate(s, st);
+}
+
+// Algorithm step 6 keeps the joined histogram of several rounds: each round's
+// int32 histogram is added to the size's int64 one and cleared.
+__global__ void k_fold_hist(int64_t *acc, int32_t *hist, int n) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < n) {
+        acc[b] += hist[b];
+        hist[b] = 0;
+    }
+}
+
+hipError_t launch_fold_hist(const SizeDev &s, int32_t *hist, hipStream_t st) {
+    hipLaunchKernelGGL(k_fold_hist, dim3((s.n_bins + 255) / 256), dim3(256), 0, st, s.hist64, hist, s.n_bins);
+    return hipGetLastError();
+}
+
+hipError_t launch_update64(const SizeDev &s, hipStream_t st) {
+    hipLaunchKernelGGL(k_update<int64_t>, dim3(1), dim3(1024), 0, st, s, s.hist64);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_tabulate(s, st);
