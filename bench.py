@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="l32",
-                    choices=["l32", "recursion8", "batched", "l128", "thermo", "fig2", "learned", "copy"])
+                    choices=["l32", "recursion8", "batched", "l128", "thermo", "fig2", "topup", "learned", "copy"])
     ap.add_argument("--rounds", type=int, default=None)
     ap.add_argument("--chains", type=int, default=None)
     ap.add_argument("--sweeps", type=int, default=None)
@@ -373,6 +373,68 @@ def bench_fig2(a, torch, mc):
     return res
 
 
+def bench_topup(a, torch, mc):
+    """Algorithm step 6 with the energy ordering of Sec. 2's remark: the Fig. 2
+    setting (L = 20, 32 chains, one bin per level, seed 1, from ln w = 0), but
+    each iteration is mc_iterate_topup: rounds of at most M_node = 100 sweeps
+    until M_total = 2.5e5 configurations (10^8 attempts) are kept.  Joints in
+    chain order (mode 0), in energy order (mode 2) and the naive splice
+    (mode 1) are compared by retention, rounds and sweeps per iteration,
+    iterations to the first flat histogram and the energy of code (ii) against
+    Kaufman's exact energy of the 20 x 20 torus."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import exact_ising as X
+
+    L, P, M = 20, a.chains or 32, a.sweeps or 100
+    N = L * L
+    m_total = int(round(1e8 / N))
+    iters = a.iters or 200
+    betas = np.round(np.linspace(0.05, 1.0, 20), 4)
+    exact = np.array([X.mean_energy_exact(L, b) for b in betas])
+    res = base_record(a, 0.0, 0.0, {"workload": "Algorithm step 6: L=20, %d chains, rounds of at most %d sweeps "
+                                                "until %d configurations are kept, %d iterations from ln w = 0, "
+                                                "one bin per level, seed 1" % (P, M, m_total, iters),
+                                    "L": L, "chains": P, "max_sweeps_per_round": M, "m_total": m_total,
+                                    "iterations": iters})
+    total_att, total_s = 0, 0.0
+    res["modes"] = {}
+    for mode, name in ((0, "detailed_balance_chain_order"), (2, "detailed_balance_energy_order"), (1, "naive")):
+        ctx = mc.Context([(L, P, 1, 0)])
+        tr, h, cut = ctx.new_trace(M), ctx.new_hist(), ctx.new_cut()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats = []
+        for it in range(iters):
+            stats.append(ctx.iterate_topup(m_total, M, tr, h, cut, mode=mode))
+            if (it + 1) % 50 == 0:
+                log("bench topup: mode %d, iteration %d (%.1f s)" % (mode, it + 1, time.perf_counter() - t0))
+        dt = time.perf_counter() - t0
+        _, first_flat, _, _ = ctx.progress()
+        e = ctx.thermo(betas)[0]
+        ctx.close()
+        rounds = np.array([s_[0] for s_ in stats])
+        sweeps = np.array([s_[1] for s_ in stats])
+        kept = np.array([s_[2] for s_ in stats])
+        gen = sweeps * P
+        dev = (e - exact) / N
+        hi = betas < 0.35
+        total_att += int(gen.sum()) * N
+        total_s += dt
+        res["modes"][name] = {
+            "first_flat_iteration": first_flat or None,
+            "retention_all": float(kept.sum() / gen.sum()),
+            "retention_last_50": float(kept[-50:].sum() / gen[-50:].sum()),
+            "rounds_per_iteration_mean": float(rounds.mean()),
+            "sweeps_per_iteration_last_50": float(sweeps[-50:].mean()),
+            "generated_per_kept_last_50": float(gen[-50:].sum() / kept[-50:].sum()),
+            "max_abs_dE_per_site_beta_lt_0.35": float(np.max(np.abs(dev[hi]))),
+            "max_abs_dE_per_site_beta_ge_0.35": float(np.max(np.abs(dev[~hi]))),
+            "seconds": dt}
+    res["value"] = total_att / total_s
+    res["ms_per_step"] = total_s / (3 * iters) * 1e3
+    return res
+
+
 def bench_learned(a, torch, mc):
     """The learned initial weight: the network is trained on converged weights
     of L = 8, 16 and 32, and proposes the weight of L = 64; iterations to the
@@ -450,6 +512,8 @@ def main():
         res = bench_thermo(a, torch, mc)
     elif a.workload == "fig2":
         res = bench_fig2(a, torch, mc)
+    elif a.workload == "topup":
+        res = bench_topup(a, torch, mc)
     elif a.workload == "learned":
         res = bench_learned(a, torch, mc)
     else:
