@@ -17,9 +17,13 @@ iterations from ln w = 0), batched (L = 16, 24, 32, 48, 64, 2048 chains each,
 graph-captured iterations), l128 (L = 128, 8192 chains), thermo (the reduced
 reweighting of code (ii) at L = 256 for 4096 inverse temperatures), fig2 (the
 comparison of Fig. 2: detailed-balance joints against naive splices at L = 20,
-measured by code (ii) against the exact energy), learned (iterations to flat at
-L = 64 from the network's proposal against ln w = 0), and copy (a plain device
-copy of known size, to calibrate the HBM byte counters).
+measured by code (ii) against the exact energy), fig1 (the comparison of
+Fig. 1 at L = 64 and 128: weights from the learned initialiser, E, C, F, S of
+code (ii) against the exact finite lattice), topup (Algorithm step 6 with
+joints in chain order, in energy order and naive, at L = 20), learned
+(iterations to flat at L = 64 from the network's proposal against ln w = 0),
+and copy (a plain device copy of known size, to calibrate the HBM byte
+counters).
 """
 import argparse
 import hashlib
@@ -53,7 +57,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="l32",
-                    choices=["l32", "recursion8", "batched", "l128", "thermo", "fig2", "topup", "learned", "copy"])
+                    choices=["l32", "recursion8", "batched", "l128", "thermo", "fig1", "fig2", "topup", "learned",
+                             "copy"])
     ap.add_argument("--rounds", type=int, default=None)
     ap.add_argument("--chains", type=int, default=None)
     ap.add_argument("--sweeps", type=int, default=None)
@@ -62,6 +67,7 @@ def parse():
     ap.add_argument("--cpu-sweeps", type=int, default=4000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
+    ap.add_argument("--out-npz", default=None, help="fig1: also save the L = 64 and L = 128 weights there")
     return ap.parse_args()
 
 
@@ -435,6 +441,92 @@ def bench_topup(a, torch, mc):
     return res
 
 
+def bench_fig1(a, torch, mc):
+    """The comparison of Fig. 1 (Sec. 5) at L = 128, the compiled size nearest
+    the paper's L = 100: E/N, C, F/N and S/N from code (ii) against the exact
+    finite-lattice values (Kaufman's ln Z and its beta derivatives).  The
+    weight comes from the learned initialiser instead of 1300 iterations:
+    converged weights of L = 8, 16, 32 (recursions from ln w = 0) train the
+    network, its proposal for L = 64 is run to flat, the network is trained
+    again with L = 64 added, and its proposal for L = 128 is run to flat."""
+    from paper_0812_2964_amd.learned import Initializer, run_to_flat
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import mpmath
+    import exact_ising as X
+
+    P, M = a.chains or 4096, a.sweeps or 2000
+    P_big = 8192
+    cap = a.iters or 150
+    L = 128
+    N = L * L
+    t0 = time.perf_counter()
+    ini = Initializer(seed=1)
+    stages, att = {}, 0
+    for Ls, c in [(8, 60), (16, 200), (32, 400)]:
+        w, flat, done = run_to_flat(Ls, P, M, c, extra=4)
+        stages[Ls] = {"from": "ln w = 0", "first_flat": flat, "iterations": done}
+        att += done * P * M * Ls * Ls
+        if flat is not None:
+            ini.add(Ls, w)
+    ini.fit(steps=4000, lr=2e-3)
+    log("bench fig1: trained on L = 8, 16, 32 (%.1f s)" % (time.perf_counter() - t0))
+    w64, flat, done = run_to_flat(64, P, M, cap, lnW0=ini.predict(64), extra=4)
+    stages[64] = {"from": "network (8, 16, 32)", "first_flat": flat, "iterations": done}
+    att += done * P * M * 64 * 64
+    if flat is not None:
+        ini.add(64, w64)
+        ini.fit(steps=4000, lr=2e-3)
+    log("bench fig1: L = 64 flat at %s, retrained (%.1f s)" % (flat, time.perf_counter() - t0))
+    w128, flat, done = run_to_flat(L, P_big, M, cap, lnW0=ini.predict(L), extra=4,
+                                   progress=lambda d: log("bench fig1: L = 128, %d iterations" % d)
+                                   if d % 20 == 0 else None)
+    stages[L] = {"from": "network (8, 16, 32, 64)", "first_flat": flat, "iterations": done, "chains": P_big}
+    att += done * P_big * M * N
+    dt = time.perf_counter() - t0
+    if a.out_npz:
+        np.savez(a.out_npz, lnW64=w64, lnW128=w128)
+    betas = np.round(np.concatenate([np.arange(0.1, 0.4, 0.05), np.arange(0.40, 0.48, 0.01),
+                                     np.arange(0.5, 1.01, 0.1)]), 4)
+
+    def compare(Ls, w):
+        Ns = Ls * Ls
+        ctx = mc.Context([(Ls, 2, 1, 1)])
+        ctx.init_weights(w)
+        e, c, f, s_ = ctx.thermo(betas)
+        ctx.close()
+        ex = {"E": [], "C": [], "F": [], "S": []}
+        with mpmath.workprec(300):
+            h = mpmath.mpf("1e-30")
+            for b in betas:
+                bb = mpmath.mpf(float(b))
+                z0, zp, zm = X.kaufman_lnZ(Ls, bb), X.kaufman_lnZ(Ls, bb + h), X.kaufman_lnZ(Ls, bb - h)
+                E = -(zp - zm) / (2 * h)
+                ex["E"].append(float(E))
+                ex["C"].append(float(bb * bb * (zp - 2 * z0 + zm) / (h * h)))
+                ex["F"].append(float(-z0 / bb))
+                ex["S"].append(float(bb * E + z0))
+        ex = {k: np.array(v) for k, v in ex.items()}
+        got = {"E": e, "C": c, "F": f, "S": s_}
+        return {"per_site": {k: (v / Ns).tolist() for k, v in got.items()},
+                "exact_per_site": {k: (v / Ns).tolist() for k, v in ex.items()},
+                "max_abs_dev_per_site": {k: float(np.max(np.abs(got[k] - ex[k])) / Ns) for k in got},
+                "max_rel_dev_C": float(np.max(np.abs(c - ex["C"]) / ex["C"])),
+                "C_peak": {"beta_exact": float(betas[np.argmax(ex["C"])]), "beta": float(betas[np.argmax(c)]),
+                           "C_per_site_exact": float(ex["C"].max() / Ns), "C_per_site": float(c.max() / Ns)}}
+
+    res = base_record(a, att / dt, dt * 1e3,
+                      {"workload": "Fig. 1 comparison at L=%d (and L=64): learned initial weight (network trained on "
+                                   "converged ln w of L=8, 16, 32, then 64), recursion to flat with %d chains x %d "
+                                   "sweeps per iteration, width-8 bins, seed 1, cap %d; code (ii) against the exact "
+                                   "finite lattice" % (L, P_big, M, cap), "L": L, "chains": P_big,
+                       "sweeps_per_iter": M, "cap": cap})
+    res["stages"] = {str(k): v for k, v in stages.items()}
+    res["betas"] = betas.tolist()
+    res["L64"] = compare(64, w64)
+    res["L128"] = compare(L, w128)
+    return res
+
+
 def bench_learned(a, torch, mc):
     """The learned initial weight: the network is trained on converged weights
     of L = 8, 16 and 32, and proposes the weight of L = 64; iterations to the
@@ -514,6 +606,8 @@ def main():
         res = bench_fig2(a, torch, mc)
     elif a.workload == "topup":
         res = bench_topup(a, torch, mc)
+    elif a.workload == "fig1":
+        res = bench_fig1(a, torch, mc)
     elif a.workload == "learned":
         res = bench_learned(a, torch, mc)
     else:
