@@ -120,7 +120,7 @@ def base_record(a, value, ms_per_step, config, dtype="u32"):
 def kernel_name(kind, L):
     return {0: "k_sweep_lds<%d,true>", 1: "k_sweep_lds<%d,false>", 2: "k_sweep_glb<%d>", 3: "k_sweep_generic",
             4: "k_sweep_pc<%d>", 5: "k_sweep_big<%d,true>", 6: "k_sweep_big<%d,false>",
-            7: "k_sweep_pcq<%d>"}[kind].replace("%d", str(L))
+            7: "k_sweep_pcq<%d>", 8: "k_sweep_bigq<%d,true>", 9: "k_sweep_bigq<%d,false>"}[kind].replace("%d", str(L))
 
 
 def roofline(attempts, kernel_s, traffic):

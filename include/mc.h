@@ -221,10 +221,15 @@ mc_status mc_get_progress(mc_ctx *ctx, int32_t size_idx, int32_t *updates, int32
      6  as 5 with the per-bin thresholds read from global memory
      7  as 4 with four lanes per chain: each step decides four sites, the
         second pair under each of the four outcomes of the first
-        (8 <= L <= 64, at most 16 chains per workgroup).
-   By default 8 <= L <= 64 run kind 7 with 16 chains per workgroup and
-   L = 128, 256 kind 5 (else 6).  mc_set_chains_per_block picks kind 7 for
-   at most 16 chains per workgroup, else kind 4, where they fit.
+        (8 <= L <= 64, at most 16 chains per workgroup)
+     8  as 5 with four lanes per chain as in 7 (L = 128, 256, at most 32
+        chains per workgroup: up to two consumer waves of 16 chains)
+     9  as 8 with the per-bin thresholds read from global memory.
+   By default 8 <= L <= 64 run kind 7 with 16 chains per workgroup, and
+   L = 128, 256 kind 8 (else 9) with 16 chains per workgroup, or 32 when there
+   are more chains than 16 per compute unit.  mc_set_chains_per_block picks
+   kind 7 (L <= 64) or 8 / 9 (L >= 128) where the chains per workgroup allow
+   it (at most 16, resp. 32), else kind 4 or 5 / 6.
    mc_autotune: times probe_sweeps sweeps of every size on copies of the chain
    state for 16, 32 and 64 chains per workgroup, with the producer/consumer
    kinds and with the one-wave kinds, and keeps the fastest; when the sizes

@@ -103,20 +103,19 @@ void free_size(SizeDev &d) {
     d = SizeDev{};
 }
 
-// Default launch: for large lattices the streamed-row kernel with the per-bin
-// thresholds in LDS (32 chains per workgroup first), else with them in global
-// memory; for 8 <= L <= 64 the quad-speculative kernel; otherwise the
-// producer/consumer kernel with as many chains per workgroup as fit in LDS,
-// else the single-wave kernel with the thresholds in LDS, else whatever fits.
-SizePlan default_plan(const SizeDev &d) {
+// Default launch: for large lattices the quad-speculative streamed-row kernel
+// (per-bin thresholds in LDS where they fit), 16 chains per workgroup when
+// one workgroup per compute unit then holds every chain, else 32 (two
+// consumer waves) so that they stay resident; for 8 <= L <= 64 the
+// quad-speculative kernel; otherwise the producer/consumer pair kernel with
+// the most chains per workgroup that fits, then the one-wave kernels.
+SizePlan default_plan(const SizeDev &d, int n_cu) {
     if (d.L >= 128) {
-        const int order[4] = {32, 16, 64, 8};
-        for (int cpb : order) {
-            SizePlan q = plan_sweeps(d, cpb, true);
-            if (q.kind == kSweepBig) return q;
-        }
-        SizePlan q = plan_sweeps(d, 16, true);
-        if (q.kind == kSweepBigGlb) return q;
+        const int cpb = (int64_t)d.P > 16ll * n_cu ? 32 : 16;
+        SizePlan q = plan_sweeps(d, cpb, true);
+        if (q.kind == kSweepBigQ || q.kind == kSweepBigQGlb) return q;
+        q = plan_sweeps(d, 64, true);
+        if (q.kind == kSweepBig || q.kind == kSweepBigGlb) return q;
     }
     if (d.L >= 8 && d.L <= 64) {
         // the quad-speculative kernel at 16 chains per workgroup: fastest at
@@ -444,7 +443,7 @@ mc_status mc_create(const mc_size *sizes, int32_t n_sizes, void *hip_stream, mc_
         if (e == hipSuccess) e = launch_tabulate(d, ctx->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
         if (e != hipSuccess) st = hip_fail(nullptr, e, "context initialisation");
-        h.plan = default_plan(d);
+        h.plan = default_plan(d, ctx->n_cu);
     }
     if (st == MC_OK) {
         hipError_t e = rebuild_launch(ctx);

@@ -47,6 +47,8 @@ enum SweepKind : int32_t {
     kSweepBig = 5,      // L >= 128: rows streamed from global memory, per-bin thresholds in LDS
     kSweepBigGlb = 6,   // the same with the per-bin thresholds read from global memory
     kSweepPCQ = 7,      // as kSweepPC with four lanes per chain deciding four sites per step (8 <= L <= 64)
+    kSweepBigQ = 8,     // as kSweepBig with four lanes per chain deciding four sites per step
+    kSweepBigQGlb = 9,  // the same with the per-bin thresholds read from global memory
 };
 
 struct SizePlan {

@@ -981,6 +981,220 @@ __global__ __launch_bounds__(kPcThreads) void k_sweep_big(PcParams p) {
     sweep_tile_big<L, TAB_LDS>(p.s, blockIdx.x * p.cpb, p.cpb, p.R, p.M, p.trace, p.hist, smem);
 }
 
+// ---------------------------------------------------------------------------
+// Quad-speculative sweeps of large lattices (L = 128, 256): the rows streamed
+// as in k_sweep_big, each chain on the four lanes of a DPP quad deciding four
+// sites per step as in k_sweep_pcq, the thresholds from the per-bin table.
+// ---------------------------------------------------------------------------
+
+// v_perm_b32 selectors for the signed level change of a pair whose outcome is
+// k = (first site accepted) + 2 (second site accepted), from {S0 = .x,
+// S1 = .y or .z} of a build_pair_levels_q entry: 0 (code 12 gives zero
+// bytes), dx (byte 1 of S1), d0 (byte 1 of S0, i.e. byte 5), dx + d1 (byte 3
+// of S1); codes 8, 10, 9 repeat the sign bits of bytes 1, 5, 3.
+constexpr uint32_t kSelMove0 = 0x0C0C0C0Cu, kSelMove1 = 0x08080801u, kSelMove2 = 0x0A0A0A05u,
+                   kSelMove3 = 0x09090903u;
+
+__device__ __forceinline__ int pair_move(uint32_t ex, uint32_t v, uint32_t sel) {
+    return (int)__builtin_amdgcn_perm(ex, v, sel);
+}
+
+// build_pair_levels with every level change at an odd byte:
+//   .x = {0, d0, 0, 0},  .y / .z = {0, dx, 0, dx + d1} for a left neighbour
+//   that did not / did flip
+// (d = 2 - anti: d0 of site x+1 if x was rejected, dx of site x, d1 of x+1 if
+// x was accepted).
+__device__ void build_pair_levels_q(uint4 *tbl, int tid, int nthreads) {
+    auto pack = [](int b1, int b3) { return ((uint32_t)(b1 & 255) << 8) | ((uint32_t)(b3 & 255) << 24); };
+    for (int i = tid; i < 64; i += nthreads) {
+        const int qx = (i & 1) + 2 * ((i >> 2) & 1);
+        const int qx1 = ((i >> 1) & 1) + 2 * ((i >> 3) & 1);
+        const int hx = (i >> 4) & 1, hx1 = (i >> 5) & 1;
+        const int d0 = 2 - (qx1 + hx1), d1 = 2 - (qx1 + (hx1 ^ 1));
+        uint32_t v[2];
+        for (int a = 0; a < 2; ++a) {
+            const int dx = 2 - (qx + (hx ^ a));
+            v[a] = pack(dx, dx + d1);
+        }
+        tbl[i] = make_uint4(pack(d0, 0), v[0], v[1], 0u);
+    }
+}
+
+// The three thresholds a pair can need from level m (entry e, left-neighbour
+// variant V): site x, site x+1 after x was rejected, after x was accepted.
+template <bool TAB_LDS>
+__device__ __forceinline__ void bigq_thresholds(int m, uint32_t ex, uint32_t V, int bs, uint32_t B0, int sB,
+                                                const uint32_t *tabc, uint32_t &tx, uint32_t &t0, uint32_t &t1) {
+    const int mx = m + sbyte(V, 1), m0 = m + sbyte(ex, 1), m11 = m + sbyte(V, 3);
+    const uint32_t Bm = B0 + ((uint32_t)(m >> bs) << sB), Bx = B0 + ((uint32_t)(mx >> bs) << sB);
+    tx = big_threshold<TAB_LDS>(tabc, Bm + 4u * (uint32_t)(mx >> bs));
+    t0 = big_threshold<TAB_LDS>(tabc, Bm + 4u * (uint32_t)(m0 >> bs));
+    t1 = big_threshold<TAB_LDS>(tabc, Bx + 4u * (uint32_t)(m11 >> bs));
+}
+
+// One row of a large lattice on a chain's quad.  Lane j assumes outcome j of
+// each step's first pair (bit 0: its first site accepted, bit 1: its second);
+// hym is all ones when j & 2, sel_h selects its assumed level change, f0 / f1
+// its result flags (j in bits 28-29, plus bit 30 when the second pair's first
+// site is accepted).  The word a lane hands to its quad is {next level, the
+// four decisions in bits 28-31}.  Every lane of the quad stores the row words
+// it computed (the same values), so that each lane's later reads of them
+// follow its own store.
+template <int L, bool TAB_LDS>
+__device__ __forceinline__ void bigq_row(uint32_t *lat, size_t P, int c, int y, int &m, int bs, uint32_t B0, int sB,
+                                         const uint32_t *tabc, uint32_t pair_addr, const uint4 *urow, int cpb,
+                                         uint32_t hym, uint32_t sel_h, uint32_t f0, uint32_t f1) {
+    constexpr int W = L / 32;
+    const int yu = y == 0 ? L - 1 : y - 1, yd = y + 1 == L ? 0 : y + 1;
+    auto word = [&](int yy, int w) { return lat + (size_t)(yy * W + w) * P + c; };
+    uint32_t cn = *word(y, 0), un = *word(yu, 0), dn = *word(yd, 0), cnn = *word(y, 1);
+    // bond (L-1, 0) at row start: the left bond of site 0
+    uint32_t carry = ((*word(y, W - 1) >> 31) ^ cn) & 1u;
+    uint32_t c0new = 0u;
+    bool aprev = false;
+    for (int w = 0; w < W; ++w) {
+        const uint32_t cw = cn, uw = un, dw = dn;
+        // right neighbours of the word; for the last word bit 31 is site 0 as
+        // it is now (it was decided at the start of the row)
+        const uint32_t cw1 = w + 1 < W ? cnn : c0new;
+        if (w + 1 < W) {
+            cn = cnn;
+            un = *word(yu, w + 1);
+            dn = *word(yd, w + 1);
+            if (w + 2 < W) cnn = *word(y, w + 2);
+        }
+        const uint32_t xu = cw ^ uw, xd = cw ^ dw, hb = cw ^ ((cw >> 1) | (cw1 << 31));
+        const uint32_t P0 = __builtin_amdgcn_bitop3_b32(xu, xd, hb, 0x96);
+        const uint32_t P1 = __builtin_amdgcn_bitop3_b32(xu, xd, hb, 0xE8);
+        const uint32_t hs = (hb << 1) | carry;  // left bonds
+        carry = hb >> 31;
+        const uint4 *uw4 = urow + (size_t)w * 8 * cpb;
+        auto entry = [&](int p) {
+            const uint32_t idx = ((P0 >> (2 * p)) & 3u) | (((P1 >> (2 * p)) & 3u) << 2) | (((hs >> (2 * p)) & 3u) << 4);
+            return lds_load96(pair_addr + idx * 16u);
+        };
+        uint32_t fw = 0u;
+        uint4 n0 = entry(0), n1 = entry(1);
+#pragma unroll
+        for (int st = 0; st < 8; ++st) {
+            const int p = 2 * st;
+            const uint4 ea = n0, eb = n1;
+            if (st + 1 < 8) {
+                n0 = entry(p + 2);
+                n1 = entry(p + 3);
+            }
+            const uint4 u4 = uw4[st * cpb];
+            // pair p from the chain's state
+            const uint32_t V = aprev ? ea.z : ea.y;
+            uint32_t tx, t0, t1;
+            bigq_thresholds<TAB_LDS>(m, ea.x, V, bs, B0, sB, tabc, tx, t0, t1);
+            // pair p+1 from the state the assumed outcome of pair p leaves
+            const int mh = m + pair_move(ea.x, V, sel_h);
+            const uint32_t Vq = (eb.z & hym) | (eb.y & ~hym);
+            uint32_t qx, q0, q1;
+            bigq_thresholds<TAB_LDS>(mh, eb.x, Vq, bs, B0, sB, tabc, qx, q0, q1);
+            const bool bx = u4.z <= qx;
+            const uint32_t qn = bx ? q1 : q0;
+            const uint32_t sA = bx ? kSelMove3 : kSelMove2, sB2 = bx ? kSelMove1 : kSelMove0;
+            const bool bx1 = u4.w <= qn;
+            const uint32_t nxt = (uint32_t)(mh + pair_move(eb.x, Vq, bx1 ? sA : sB2));
+            const uint32_t res = nxt | (bx ? f1 : f0) | (bx1 ? 1u << 31 : 0u);
+            const uint32_t r0 = quad_bcast<0x00>(res), r1 = quad_bcast<0x55>(res);
+            const uint32_t r2 = quad_bcast<0xAA>(res), r3 = quad_bcast<0xFF>(res);
+            const bool ax = u4.x <= tx;
+            const uint32_t tn = ax ? t1 : t0;
+            const uint32_t rA = ax ? r3 : r2, rB = ax ? r1 : r0;
+            const bool ax1 = u4.y <= tn;
+            const uint32_t sel = ax1 ? rA : rB;
+            m = (int)(sel & 0x0FFFFFFFu);
+            fw |= (sel >> 28) << (4 * st);
+            aprev = (sel >> 31) != 0u;
+        }
+        const uint32_t cnew = cw ^ fw;
+        *word(y, w) = cnew;
+        if (w == 0) c0new = cnew;
+    }
+}
+
+// Chains per workgroup of the quad large-lattice kernel: up to two consumer
+// waves of 16 chains (the other waves produce), so that 8192 chains of L = 128
+// stay resident with the per-bin table in LDS.
+constexpr int kBigqMaxChains = 32;
+
+// Sweeps of chains c0 .. c0+cpb-1 (cpb <= 32) of a large lattice.  Waves
+// 0 .. nc-1 consume (nc = ceil(cpb / 16); the chain of lane l of consumer wave
+// q is c0 + 16 q + l/4), the other waves produce.
+template <int L, bool TAB_LDS>
+__device__ __forceinline__ void sweep_tile_bigq(const SizeDev &s, int c0, int cpb, int R, int64_t M, void *trace,
+                                                int32_t *hist, uint32_t *smem) {
+    constexpr int N = L * L;
+    const int r = s.tab_r, K = 2 * r + 1;
+    const BigLayout lay = big_layout(L, s.n_bins, r, cpb, R, TAB_LDS);
+    char *lds = (char *)smem;
+    uint32_t *stab = (uint32_t *)(lds + lay.tab);
+    uint4 *ptbl = (uint4 *)(lds + lay.pair);
+    uint4 *ubuf = (uint4 *)(lds + lay.ubuf);
+    const int chunk_words = R * (L / 4) * cpb;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nc = (cpb + 15) >> 4;
+    const int cl = wave * 16 + (lane >> 2), j = lane & 3;
+    const int c = c0 + cl;
+    const bool consumer = wave < nc;
+    const bool active = consumer && cl < cpb && c < s.P;
+    const bool lead = active && j == 0;  // one lane per chain for the trace, histogram and level
+    const uint32_t hym = 0u - (uint32_t)((j >> 1) & 1);
+    const uint32_t sel_h = j == 0 ? kSelMove0 : j == 1 ? kSelMove1 : j == 2 ? kSelMove2 : kSelMove3;
+    const uint32_t f0 = (uint32_t)j << 28, f1 = f0 | (1u << 30);
+    const uint32_t k0 = s.seed, k1 = (uint32_t)L;
+    const uint32_t g0 = s.ctl->g;
+    if (TAB_LDS)
+        for (int i = threadIdx.x; i < s.n_bins * K; i += blockDim.x) stab[i] = s.tabc[i];
+    build_pair_levels_q(ptbl, threadIdx.x, blockDim.x);
+    const int np = (int)blockDim.x - 64 * nc, pt = (int)threadIdx.x - 64 * nc;
+    const int per_sweep = L / R;
+    const int64_t n_chunks = M * per_sweep;
+    if (!consumer) pc_produce<L>(ubuf, R, 0u, g0, c0, cpb, k0, k1, pt, np);
+    __syncthreads();
+
+    const uint32_t B0 = (TAB_LDS ? (uint32_t)(size_t)(lds_u32 *)(stab) : 0u) + 4u * (uint32_t)r;
+    const int sB = r == 1 ? 3 : 4;  // log2(8 r)
+    const int bs = s.bin_shift;
+    const uint32_t pair_addr = (uint32_t)(size_t)(lds_u32 *)(ptbl);
+    int m = 0;
+    if (active) m = s.lev[c];
+    for (int64_t i = 0; i < n_chunks; ++i) {
+        const int64_t k = i / per_sweep;
+        const int y0 = (int)(i - k * per_sweep) * R;
+        if (active) {
+            const uint4 *ub = ubuf + (size_t)(i & 1) * chunk_words;
+            for (int rr = 0; rr < R; ++rr)
+                bigq_row<L, TAB_LDS>(s.lat, (size_t)s.P, c, y0 + rr, m, bs, B0, sB, s.tabc, pair_addr,
+                                     ub + (size_t)rr * (L / 4) * cpb + cl, cpb, hym, sel_h, f0, f1);
+            if (y0 + R == L && lead) {
+                const int ev = m - N / 2;
+                if (s.trace_bytes == 2)
+                    ((int16_t *)trace)[(size_t)c * M + k] = (int16_t)ev;
+                else
+                    ((int32_t *)trace)[(size_t)c * M + k] = ev;
+                atomicAdd(&hist[m >> bs], 1);
+            }
+        } else if (!consumer && i + 1 < n_chunks) {
+            const int64_t k1s = (i + 1) / per_sweep;
+            const int y1 = (int)(i + 1 - k1s * per_sweep) * R;
+            pc_produce<L>(ubuf + (size_t)((i + 1) & 1) * chunk_words, R, (uint32_t)y1, g0 + (uint32_t)k1s, c0, cpb,
+                          k0, k1, pt, np);
+        }
+        __syncthreads();
+    }
+    if (lead) s.lev[c] = m;
+}
+
+template <int L, bool TAB_LDS>
+__global__ __launch_bounds__(kPcThreads) void k_sweep_bigq(PcParams p) {
+    extern __shared__ __align__(16) uint32_t smem[];
+    sweep_tile_bigq<L, TAB_LDS>(p.s, blockIdx.x * p.cpb, p.cpb, p.R, p.M, p.trace, p.hist, smem);
+}
+
 // Lattice rows streamed from global memory (large L); thresholds from global.
 template <int L>
 __global__ __launch_bounds__(64) void k_sweep_glb(SweepParams p) {
@@ -1097,6 +1311,20 @@ SizePlan plan_sweeps(const SizeDev &s, int cpb, bool allow_pc) {
         p.cpb = 64;
         return p;
     }
+    if (allow_pc && big_size(s.L) && p.cpb <= kBigqMaxChains) {
+        for (int pass = 0; pass < 2; ++pass) {
+            const bool tab_lds = pass == 0;
+            for (int R = 4; R >= 1; R /= 2) {
+                const BigLayout lay = big_layout(s.L, s.n_bins, s.tab_r, p.cpb, R, tab_lds);
+                if (lay.total <= kLdsMax) {
+                    p.kind = tab_lds ? kSweepBigQ : kSweepBigQGlb;
+                    p.R = R;
+                    p.lds_bytes = lay.total;
+                    return p;
+                }
+            }
+        }
+    }
     if (allow_pc && big_size(s.L)) {
         for (int pass = 0; pass < 2; ++pass) {
             const bool tab_lds = pass == 0;
@@ -1168,9 +1396,13 @@ template <int L>
 static hipError_t prepare_L(const SizePlan &p) {
     static size_t allowed_tab = 0, allowed_notab = 0, allowed_pc = 0, allowed_big = 0, allowed_bigg = 0;
     if constexpr (L >= 128) {
+        static size_t allowed_bq = 0, allowed_bqg = 0;
         if (p.kind == kSweepBig) return allow_lds((const void *)k_sweep_big<L, true>, allowed_big, p.lds_bytes);
         if (p.kind == kSweepBigGlb)
             return allow_lds((const void *)k_sweep_big<L, false>, allowed_bigg, p.lds_bytes);
+        if (p.kind == kSweepBigQ) return allow_lds((const void *)k_sweep_bigq<L, true>, allowed_bq, p.lds_bytes);
+        if (p.kind == kSweepBigQGlb)
+            return allow_lds((const void *)k_sweep_bigq<L, false>, allowed_bqg, p.lds_bytes);
     }
     if constexpr (L >= 8 && L <= 64 && L % 4 == 0) {
         static size_t allowed_pcq = 0;
@@ -1187,12 +1419,16 @@ static hipError_t launch_L(const SweepParams &p0, const SizePlan &pl, hipStream_
     SweepParams p = p0;
     const dim3 grid((p.s.P + pl.cpb - 1) / pl.cpb), block(64);
     if constexpr (L >= 128) {
-        if (pl.kind == kSweepBig || pl.kind == kSweepBigGlb) {
+        if (pl.kind == kSweepBig || pl.kind == kSweepBigGlb || pl.kind == kSweepBigQ || pl.kind == kSweepBigQGlb) {
             PcParams q{p.s, p.M, p.trace, p.hist, pl.cpb, pl.R};
             if (pl.kind == kSweepBig)
                 hipLaunchKernelGGL((k_sweep_big<L, true>), grid, dim3(kPcThreads), pl.lds_bytes, st, q);
-            else
+            else if (pl.kind == kSweepBigGlb)
                 hipLaunchKernelGGL((k_sweep_big<L, false>), grid, dim3(kPcThreads), pl.lds_bytes, st, q);
+            else if (pl.kind == kSweepBigQ)
+                hipLaunchKernelGGL((k_sweep_bigq<L, true>), grid, dim3(kPcThreads), pl.lds_bytes, st, q);
+            else
+                hipLaunchKernelGGL((k_sweep_bigq<L, false>), grid, dim3(kPcThreads), pl.lds_bytes, st, q);
             return hipGetLastError();
         }
     }

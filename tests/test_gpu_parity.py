@@ -155,28 +155,33 @@ def _smooth_weight(L, bs, seed):
     return -0.25 * N * x * x + rng.normal(0, 0.3, nb)
 
 
-def test_large_lattice_kernels_bitexact():
-    """L = 128 with width-8 bins: the streamed-row kernel with the per-bin
-    thresholds in LDS (kind 5; 32 chains per workgroup by default, and 13) and
-    read from global memory (kind 6, 64 chains per workgroup do not leave room
-    for the table), each against the oracle over two rounds with a ragged
-    last workgroup."""
+@pytest.mark.parametrize("L,bs,cpb,kind", [(128, 1, None, 8), (128, 1, 13, 8), (128, 1, 32, 8), (128, 1, 20, 8),
+                                             (128, 1, 40, 5), (128, 1, 64, 6), (128, 0, 16, 9), (256, 1, None, 9),
+                                             (256, 1, 5, 9), (256, 1, 32, 9)])
+def test_large_lattice_kernels_bitexact(L, bs, cpb, kind):
+    """The streamed-row kernels of the large lattices against the oracle over
+    two rounds with a ragged last workgroup: four lanes per chain (the
+    default; at most 32 chains per workgroup, 17 or more on two consumer
+    waves) with the per-bin thresholds in LDS (kind 8) or, where they do not
+    fit (one level per bin at L = 128, L = 256), in global memory (kind 9);
+    one lane per chain (more than 32 chains per workgroup) with the table in
+    LDS (kind 5) or, where 64 chains leave no room for it, in global memory
+    (kind 6)."""
     mc = _mc()
-    L, P, bs, M = 128, 70, 1, 2
+    P, M = 70, 2
     w = _smooth_weight(L, bs, 11)
-    for cpb, kind in [(None, 5), (13, 5), (64, 6)]:
-        ctx = mc.Context([(L, P, 3, bs)])
-        ctx.init_weights(w)
-        if cpb is not None:
-            ctx.set_chains_per_block(cpb)
-        assert ctx.launch()[1] == kind, (cpb, ctx.launch())
-        R = O.Run(L, P, seed=3, bin_shift=bs, lnW=w)
-        for _ in range(2):
-            g = gpu_round(ctx, M)
-            o = oracle_round(R, M)
-            assert_round_equal(g, o)
-        assert_state_equal(ctx, R)
-        ctx.close()
+    ctx = mc.Context([(L, P, 3, bs)])
+    ctx.init_weights(w)
+    if cpb is not None:
+        ctx.set_chains_per_block(cpb)
+    assert ctx.launch()[1] == kind, (cpb, ctx.launch())
+    R = O.Run(L, P, seed=3, bin_shift=bs, lnW=w)
+    for _ in range(2):
+        g = gpu_round(ctx, M)
+        o = oracle_round(R, M)
+        assert_round_equal(g, o)
+    assert_state_equal(ctx, R)
+    ctx.close()
 
 
 def test_join_hand_built_traces_and_modes():
@@ -294,7 +299,8 @@ def test_bench_workload_full_size_sampled():
 
 def test_l128_workload_full_chain_count_sampled():
     """L = 128 with the workload's 8192 chains in the default launch (the
-    streamed-row kernel with the per-bin table in LDS), a non-trivial weight
+    quad streamed-row kernel, 32 chains on two consumer waves per workgroup,
+    the per-bin table in LDS), a non-trivial weight
     (at ln w = 0 every flip is accepted), four sweeps: sampled chains replayed
     by the oracle bit for bit; histograms and cut points through properties
     that hold at any size."""
@@ -304,14 +310,14 @@ def test_l128_workload_full_chain_count_sampled():
     w = _smooth_weight(L, bs, 21)
     ctx = mc.Context([(L, P, 1, bs)])
     ctx.init_weights(w)
-    assert ctx.launch()[1] == 5
+    assert ctx.launch()[:2] == (32, 8)
     tr, h, cut = ctx.new_trace(M), ctx.new_hist(), ctx.new_cut()
     ctx.run_chains(M, tr, h)
     raw = _np(h).copy()
     ctx.join(tr, cut, h)
     joined = _np(h).copy()
     levels = ctx.levels()
-    sampled = (0, 31, 32, 4095, 8191)
+    sampled = (0, 15, 16, 31, 32, 4095, 8191)  # 16: first chain of a workgroup's second consumer wave
     spins = {c: ctx.spins(c) for c in sampled}
     trace = _np(tr)
     cuts = _np(cut)
