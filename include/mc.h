@@ -178,6 +178,27 @@ mc_status mc_get_levels(mc_ctx *ctx, int32_t size_idx, int32_t *levels_host);
 mc_status mc_get_lattice(mc_ctx *ctx, int32_t size_idx, int32_t chain, uint32_t *words_host, int32_t n_words);
 mc_status mc_get_counters(mc_ctx *ctx, int32_t size_idx, int32_t *seam, uint32_t *round, uint32_t *sweep);
 
+/* Checkpoint and resume (synchronising).  The random words are counter-based
+   (their counters are the chain, the site and the global sweep and round
+   indices), so a context restored from a blob continues bit for bit as the
+   one the blob was taken from.  The blob (version 1, little-endian) holds,
+   for every size: its configuration, the host call-order state (runs since
+   the last update, the pending joint), the device counters (sweep index,
+   round, seam, retained counts, updates, flatness), the lattices, the levels
+   and ln w, under a CRC-32 (the zlib definition) of the whole blob.  The
+   thresholds are rebuilt from ln w.  Caller-owned buffers (traces,
+   histograms, cuts) are not part of it: a blob taken between mc_run_chains
+   and mc_update_weights resumes only together with the caller's histogram.
+   mc_get_state: with buf NULL, *len receives the size; otherwise buf must
+   hold *len >= that size, and *len receives it.  MC_EINVAL for a null len or
+   a short buffer.
+   mc_set_state: the context must have been created with the same sizes,
+   chain counts, seeds and bins (MC_EINVAL otherwise); a blob that fails its
+   magic, version, length or checksum, or holds a non-finite ln w, gives
+   MC_ECORRUPT and changes nothing.  Graphs of the context stay valid. */
+mc_status mc_get_state(mc_ctx *ctx, void *buf, size_t *len);
+mc_status mc_set_state(mc_ctx *ctx, const void *buf, size_t len);
+
 /* Read ln w of one size into host memory (n_bins values; synchronising). */
 mc_status mc_get_weights(mc_ctx *ctx, int32_t size_idx, double *lnW_host, int32_t n_bins);
 

@@ -25,7 +25,8 @@ EXPORTED = ["mc_create", "mc_destroy", "mc_n_bins", "mc_trace_elem_bytes", "mc_l
             "mc_get_weights", "mc_get_progress", "mc_set_chains_per_block", "mc_get_launch", "mc_autotune",
             "mc_graph_create", "mc_graph_launch", "mc_graph_destroy", "mc_sync", "mc_last_error",
             "mc_mlp_n_params", "mc_mlp_workspace_bytes", "mc_mlp_init", "mc_mlp_forward", "mc_mlp_loss_grad",
-            "mc_mlp_train", "mc_mlp_targets", "mc_mlp_predict_weights", "mc_thermo", "mc_iterate_topup"]
+            "mc_mlp_train", "mc_mlp_targets", "mc_mlp_predict_weights", "mc_thermo", "mc_iterate_topup",
+            "mc_get_state", "mc_set_state"]
 
 
 class MCError(RuntimeError):
@@ -64,6 +65,8 @@ def lib():
     L.mc_join.argtypes = [p, i32, p, i64, p, p, i32]
     L.mc_update_weights.argtypes = [p, i32, p, p, p, p]
     L.mc_iterate_topup.argtypes = [p, i64, i64, i32, p, p, p, i32, p, p, p, p]
+    L.mc_get_state.argtypes = [p, p, ctypes.POINTER(ctypes.c_size_t)]
+    L.mc_set_state.argtypes = [p, p, ctypes.c_size_t]
     L.mc_get_levels.argtypes = [p, i32, p]
     L.mc_get_lattice.argtypes = [p, i32, i32, p, i32]
     L.mc_get_counters.argtypes = [p, i32, p, p, p]
@@ -232,6 +235,20 @@ class Context:
                                       _dev_ptr(cut, torch.int32, P, "cut"), int(mode), ctypes.byref(rounds),
                                       ctypes.byref(sweeps), ctypes.byref(kept), ctypes.byref(flat)))
         return rounds.value, sweeps.value, kept.value, bool(flat.value)
+
+    def get_state(self):
+        """Checkpoint of the whole context as bytes (mc_get_state)."""
+        n = ctypes.c_size_t(0)
+        _check(lib().mc_get_state(self._h, None, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        _check(lib().mc_get_state(self._h, buf, ctypes.byref(n)))
+        return buf.raw[: n.value]
+
+    def set_state(self, blob):
+        """Resume from a checkpoint taken by get_state (mc_set_state)."""
+        blob = bytes(blob)
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _check(lib().mc_set_state(self._h, buf, len(blob)))
 
     # -- inspection -------------------------------------------------------
     def levels(self, i=0):

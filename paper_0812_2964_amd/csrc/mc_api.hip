@@ -370,6 +370,36 @@ static hipError_t trace_ends(mc_ctx *ctx, const SizeDev &d, const void *trace_de
     return hipSuccess;
 }
 
+// CRC-32 of the IEEE 802.3 / zlib definition (reflected polynomial
+// 0xEDB88320, initial and final complement), table driven.
+static uint32_t crc32_of(const unsigned char *p, size_t n) {
+    static uint32_t table[256];
+    static bool ready = false;
+    if (!ready) {
+        for (uint32_t i = 0; i < 256; ++i) {
+            uint32_t c = i;
+            for (int k = 0; k < 8; ++k) c = (c & 1u) ? 0xEDB88320u ^ (c >> 1) : c >> 1;
+            table[i] = c;
+        }
+        ready = true;
+    }
+    uint32_t c = 0xFFFFFFFFu;
+    for (size_t i = 0; i < n; ++i) c = table[(c ^ p[i]) & 0xFFu] ^ (c >> 8);
+    return c ^ 0xFFFFFFFFu;
+}
+
+// State blob: a 24-byte header {"MCS1", version, crc, n_sizes, total bytes}
+// and per size {L, n_chains, seed, bin_shift, W, n_bins, pending, last_M,
+// the Ctl counters field by field, lattice words, levels, ln w}, all
+// little-endian; the CRC-32 covers the whole blob with its crc field zero.
+constexpr uint32_t kStateVersion = 1;
+constexpr size_t kStateHeader = 24;
+
+static size_t state_size_of(const SizeDev &d) {
+    return 6 * 4 + 2 * 8 + (4 * 4 + 2 * 8 + 2 * 4) + (size_t)d.L * d.W * d.P * 4 + (size_t)d.P * 4 +
+           (size_t)d.n_bins * 8;
+}
+
 void mcgpu::set_last_error(const char *msg) { g_err = msg; }
 
 extern "C" {
@@ -685,6 +715,142 @@ mc_status mc_get_weights(mc_ctx *ctx, int32_t i, double *lnW_host, int32_t n_bin
     if (!lnW_host || n_bins != d.n_bins) return fail(MC_EINVAL, "need %d bins", d.n_bins);
     HIP_OR_FAIL(ctx, hipMemcpyAsync(lnW_host, d.lnW, (size_t)d.n_bins * 8, hipMemcpyDeviceToHost, ctx->stream));
     HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+    return MC_OK;
+}
+
+mc_status mc_get_state(mc_ctx *ctx, void *buf, size_t *len) {
+    mc_status st = check_ctx(ctx);
+    if (st != MC_OK) return st;
+    if (!len) return fail(MC_EINVAL, "null length pointer");
+    size_t need = kStateHeader;
+    for (const auto &h : ctx->sizes) need += state_size_of(h.dev);
+    if (!buf) {
+        *len = need;
+        return MC_OK;
+    }
+    if (*len < need) return fail(MC_EINVAL, "the state needs %zu bytes, the buffer has %zu", need, *len);
+    unsigned char *o = (unsigned char *)buf;
+    size_t at = 0;
+    auto put = [&](const void *v, size_t n) {
+        std::memcpy(o + at, v, n);
+        at += n;
+    };
+    auto put32 = [&](uint32_t v) { put(&v, 4); };
+    auto put64 = [&](uint64_t v) { put(&v, 8); };
+    put("MCS1", 4);
+    put32(kStateVersion);
+    put32(0u);  // crc, filled in below
+    put32((uint32_t)ctx->sizes.size());
+    put64((uint64_t)need);
+    for (const auto &h : ctx->sizes) {
+        const SizeDev &d = h.dev;
+        Ctl c{};
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(&c, d.ctl, sizeof c, hipMemcpyDeviceToHost, ctx->stream));
+        const size_t lat_b = (size_t)d.L * d.W * d.P * 4;
+        const size_t base = at + 6 * 4 + 2 * 8 + (4 * 4 + 2 * 8 + 2 * 4);
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(o + base, d.lat, lat_b, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(o + base + lat_b, d.lev, (size_t)d.P * 4, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(o + base + lat_b + (size_t)d.P * 4, d.lnW, (size_t)d.n_bins * 8,
+                                        hipMemcpyDeviceToHost, ctx->stream));
+        HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+        put32((uint32_t)d.L);
+        put32((uint32_t)d.P);
+        put32(d.seed);
+        put32((uint32_t)d.bin_shift);
+        put32((uint32_t)d.W);
+        put32((uint32_t)d.n_bins);
+        put64((uint64_t)h.pending);
+        put64((uint64_t)h.last_M);
+        put32(c.g);
+        put32(c.r);
+        put32((uint32_t)c.sigma);
+        put32((uint32_t)c.flat);
+        put64((uint64_t)c.retained);
+        put64((uint64_t)c.retained_last);
+        put32((uint32_t)c.iter);
+        put32((uint32_t)c.flat_iter);
+        at = base + lat_b + (size_t)d.P * 4 + (size_t)d.n_bins * 8;
+    }
+    const uint32_t crc = crc32_of(o, need);
+    std::memcpy(o + 8, &crc, 4);
+    *len = need;
+    return MC_OK;
+}
+
+mc_status mc_set_state(mc_ctx *ctx, const void *buf, size_t len) {
+    mc_status st = check_ctx(ctx);
+    if (st != MC_OK) return st;
+    if (!buf) return fail(MC_EINVAL, "null state");
+    const unsigned char *b = (const unsigned char *)buf;
+    if (len < kStateHeader || std::memcmp(b, "MCS1", 4) != 0) return fail(MC_ECORRUPT, "not a state blob");
+    uint32_t version, crc, n_sizes;
+    uint64_t total;
+    std::memcpy(&version, b + 4, 4);
+    std::memcpy(&crc, b + 8, 4);
+    std::memcpy(&n_sizes, b + 12, 4);
+    std::memcpy(&total, b + 16, 8);
+    if (version != kStateVersion) return fail(MC_ECORRUPT, "state version %u, expected %u", version, kStateVersion);
+    if (total != len) return fail(MC_ECORRUPT, "state length %zu, the blob says %llu", len, (unsigned long long)total);
+    std::vector<unsigned char> copy(b, b + len);
+    std::memset(copy.data() + 8, 0, 4);
+    if (crc32_of(copy.data(), len) != crc) return fail(MC_ECORRUPT, "state checksum mismatch");
+    if (n_sizes != ctx->sizes.size())
+        return fail(MC_EINVAL, "the state has %u sizes, the context %zu", n_sizes, ctx->sizes.size());
+    // validate every size before touching any
+    size_t at = kStateHeader;
+    auto get32 = [&](size_t pos) {
+        uint32_t v;
+        std::memcpy(&v, b + pos, 4);
+        return v;
+    };
+    auto get64 = [&](size_t pos) {
+        uint64_t v;
+        std::memcpy(&v, b + pos, 8);
+        return v;
+    };
+    for (const auto &h : ctx->sizes) {
+        const SizeDev &d = h.dev;
+        if (at + 24 > len) return fail(MC_ECORRUPT, "state too short");
+        if ((int)get32(at) != d.L || (int)get32(at + 4) != d.P || get32(at + 8) != d.seed ||
+            (int)get32(at + 12) != d.bin_shift || (int)get32(at + 16) != d.W || (int)get32(at + 20) != d.n_bins)
+            return fail(MC_EINVAL, "the state's sizes differ from the context's");
+        if (at + state_size_of(d) > len) return fail(MC_ECORRUPT, "state too short");
+        const size_t lnw = at + state_size_of(d) - (size_t)d.n_bins * 8;
+        for (int k = 0; k < d.n_bins; ++k) {
+            double v;
+            std::memcpy(&v, b + lnw + (size_t)k * 8, 8);
+            if (!std::isfinite(v)) return fail(MC_ECORRUPT, "ln w[%d] in the state is not finite", k);
+        }
+        at += state_size_of(d);
+    }
+    if (at != len) return fail(MC_ECORRUPT, "state length does not match its sizes");
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+    at = kStateHeader;
+    for (auto &h : ctx->sizes) {
+        SizeDev &d = h.dev;
+        Ctl c{};
+        c.g = get32(at + 40);
+        c.r = get32(at + 44);
+        c.sigma = (int32_t)get32(at + 48);
+        c.flat = (int32_t)get32(at + 52);
+        c.retained = (int64_t)get64(at + 56);
+        c.retained_last = (int64_t)get64(at + 64);
+        c.iter = (int32_t)get32(at + 72);
+        c.flat_iter = (int32_t)get32(at + 76);
+        const size_t base = at + 80;
+        const size_t lat_b = (size_t)d.L * d.W * d.P * 4;
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(d.ctl, &c, sizeof c, hipMemcpyHostToDevice, ctx->stream));
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(d.lat, b + base, lat_b, hipMemcpyHostToDevice, ctx->stream));
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(d.lev, b + base + lat_b, (size_t)d.P * 4, hipMemcpyHostToDevice, ctx->stream));
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(d.lnW, b + base + lat_b + (size_t)d.P * 4, (size_t)d.n_bins * 8,
+                                        hipMemcpyHostToDevice, ctx->stream));
+        HIP_OR_FAIL(ctx, hipMemsetAsync(d.hist64, 0, (size_t)d.n_bins * 8, ctx->stream));
+        HIP_OR_FAIL(ctx, launch_tabulate(d, ctx->stream));
+        HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+        h.pending = (int64_t)get64(at + 24);
+        h.last_M = (int64_t)get64(at + 32);
+        at += state_size_of(d);
+    }
     return MC_OK;
 }
 

@@ -1,0 +1,134 @@
+"""Checkpoint and resume (mc_get_state / mc_set_state): a run interrupted after
+iteration k and resumed from its blob in a fresh context continues bit for bit
+as the uninterrupted run; the blob's checksum is the zlib CRC-32; damaged,
+truncated or mismatched blobs are refused without changing the context."""
+import os
+import sys
+import zlib
+
+import numpy as np
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(HERE))
+
+pytestmark = pytest.mark.gpu
+
+
+def _mc():
+    import paper_0812_2964_amd as mc
+
+    return mc
+
+
+def _iterate(ctx, M, n, mode=0):
+    """n iterations (run, joint, update) of every size; returns per iteration
+    the traces, the joined histograms and ln w, as numpy arrays."""
+    out = []
+    sizes = len(ctx.sizes)
+    for _ in range(n):
+        trs = [ctx.new_trace(M, i) for i in range(sizes)]
+        hs = [ctx.new_hist(i) for i in range(sizes)]
+        cuts = [ctx.new_cut(i) for i in range(sizes)]
+        ctx.run_chains(M, trs, hs)
+        rec = []
+        for i in range(sizes):
+            ctx.join(trs[i], cuts[i], hs[i], mode=mode, i=i)
+            joined = hs[i].cpu().numpy().copy()
+            w, flat, ret = ctx.update_weights(hs[i], i=i)
+            rec.append((trs[i].cpu().numpy(), cuts[i].cpu().numpy(), joined, w.view(np.uint64), flat, ret))
+        out.append(rec)
+    return out
+
+
+def _same(a, b):
+    assert len(a) == len(b)
+    for ra, rb in zip(a, b):
+        for xa, xb in zip(ra, rb):
+            for ya, yb in zip(xa, xb):
+                if isinstance(ya, np.ndarray):
+                    assert np.array_equal(ya, yb)
+                else:
+                    assert ya == yb
+
+
+@pytest.mark.parametrize("sizes,mode", [([(32, 130, 7, 1)], 0), ([(16, 64, 3, 1), (48, 40, 3, 0)], 0),
+                                        ([(128, 20, 5, 1)], 0), ([(20, 32, 1, 0)], 2)])
+def test_resume_equals_uninterrupted(sizes, mode):
+    mc = _mc()
+    M, k, n = 40, 3, 3
+    A = mc.Context(sizes)
+    _iterate(A, M, k, mode)
+    blob = A.get_state()
+    rest_a = _iterate(A, M, n, mode)
+    end_a = [(A.counters(i), A.progress(i), A.levels(i)) for i in range(len(sizes))]
+    A.close()
+    B = mc.Context(sizes)
+    _iterate(B, 7, 1, mode)  # some other history, overwritten by the resume
+    B.set_state(blob)
+    rest_b = _iterate(B, M, n, mode)
+    _same(rest_a, rest_b)
+    for i in range(len(sizes)):
+        ca, pa, la = end_a[i]
+        assert B.counters(i) == ca and B.progress(i) == pa and np.array_equal(B.levels(i), la)
+    B.close()
+
+
+def test_resume_in_a_graph_and_mid_iteration():
+    """The restored device counters drive graph replays; a blob taken between
+    the run and the joint resumes together with the caller's histogram."""
+    import torch
+
+    mc = _mc()
+    L, P, M = 16, 64, 50
+    A = mc.Context([(L, P, 9, 1)])
+    _iterate(A, M, 2)
+    tr, h, cut = A.new_trace(M), A.new_hist(), A.new_cut()
+    A.run_chains(M, tr, h)
+    blob = A.get_state()
+    h_saved, tr_saved = h.clone(), tr.clone()
+    A.join(tr, cut, h)
+    wa, fa, ra = A.update_weights(h)
+    g = A.graph(M, 3, [tr], [h], [cut])
+    g.launch()
+    torch.cuda.synchronize()
+    g.close()
+    wa2 = A.weights()
+    A.close()
+    B = mc.Context([(L, P, 9, 1)])
+    B.set_state(blob)
+    h2, tr2, cut2 = h_saved.clone(), tr_saved.clone(), B.new_cut()
+    B.join(tr2, cut2, h2)
+    wb, fb, rb = B.update_weights(h2)
+    assert np.array_equal(wa.view(np.uint64), wb.view(np.uint64)) and (fa, ra) == (fb, rb)
+    g = B.graph(M, 3, [tr2], [h2], [cut2])
+    g.launch()
+    torch.cuda.synchronize()
+    g.close()
+    assert np.array_equal(wa2.view(np.uint64), B.weights().view(np.uint64))
+    B.close()
+
+
+def test_blob_checksum_and_refusals():
+    mc = _mc()
+    A = mc.Context([(8, 16, 1, 1)])
+    _iterate(A, 20, 2)
+    blob = A.get_state()
+    assert blob[:4] == b"MCS1"
+    crc = int.from_bytes(blob[8:12], "little")
+    assert crc == zlib.crc32(blob[:8] + b"\0\0\0\0" + blob[12:])
+    before = A.get_state()
+    bad = bytearray(blob)
+    bad[len(bad) // 2] ^= 0x40
+    for damaged in (bytes(bad), blob[:-8], b"XXXX" + blob[4:], blob[:10]):
+        with pytest.raises(mc.MCError) as e:
+            A.set_state(damaged)
+        assert "MC_ECORRUPT" in str(e.value)
+    assert A.get_state() == before  # nothing changed
+    for other in ([(8, 16, 2, 1)], [(8, 17, 1, 1)], [(8, 16, 1, 0)], [(8, 16, 1, 1), (8, 16, 1, 1)]):
+        B = mc.Context(other)
+        with pytest.raises(mc.MCError) as e:
+            B.set_state(blob)
+        assert "MC_EINVAL" in str(e.value)
+        B.close()
+    A.close()
