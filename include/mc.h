@@ -70,6 +70,11 @@ typedef struct {
     int32_t n_chains;  /* p of the paper, >= 1, <= 2^20                        */
     uint32_t seed;     /* Philox key word 0 (word 1 is L)                      */
     int32_t bin_shift; /* 0: one bin per level; 1: two levels (8 energy units) */
+    uint32_t chain_offset; /* global index of chain 0: the chains are chains
+                              chain_offset .. chain_offset + n_chains - 1 of a
+                              run split over several contexts (or GPUs), and
+                              every random word is keyed by the global index;
+                              0 for a whole run.  offset + n_chains <= 2^32 */
 } mc_size;
 
 /* Create a context on the current HIP device for n_sizes (1..16) lattice
@@ -177,6 +182,16 @@ mc_status mc_iterate_topup(mc_ctx *ctx, int64_t m_total, int64_t m_max, int32_t 
 mc_status mc_get_levels(mc_ctx *ctx, int32_t size_idx, int32_t *levels_host);
 mc_status mc_get_lattice(mc_ctx *ctx, int32_t size_idx, int32_t chain, uint32_t *words_host, int32_t n_words);
 mc_status mc_get_counters(mc_ctx *ctx, int32_t size_idx, int32_t *seam, uint32_t *round, uint32_t *sweep);
+
+/* The seam the next mc_join of one size starts from (Algorithm step 4: the
+   level of the last configuration kept before its first chain; -1 = none, so
+   that its first chain is kept whole).  For a run split into blocks of chains
+   (chain_offset), each block's joint starts from the seam the previous
+   block's joint ended with (mc_get_counters); the blocks joined in order then
+   keep exactly what one joint over all chains keeps.  Only the joint reads
+   the seam, so it may be set between a block's run and its joint.
+   Synchronising.  MC_EINVAL for a seam outside -1..N. */
+mc_status mc_set_seam(mc_ctx *ctx, int32_t size_idx, int32_t seam);
 
 /* Checkpoint and resume (synchronising).  The random words are counter-based
    (their counters are the chain, the site and the global sweep and round

@@ -48,7 +48,7 @@ def lib():
     L.orc_level_reachable.restype = ctypes.c_int
     L.orc_tabulate.argtypes = [_i32, _i32, _p, _p]
     L.orc_sweeps.argtypes = [_i32, _u32, _i32, _u32, _p, _p, _u32, _i64, _p, _p, _p]
-    L.orc_join.argtypes = [_i32, _i32, _u32, _i32, _i64, _p, _p, _p, _u32, _i32, _p, _p, _p, _p]
+    L.orc_join.argtypes = [_i32, _i32, _u32, _u32, _i32, _i64, _p, _p, _p, _u32, _i32, _p, _p, _p, _p]
     L.orc_energy_order.argtypes = [_i32, _p, _p, _i32, _p]
     L.orc_update.argtypes = [_i32, _i32, _p, _p]
     L.orc_update.restype = ctypes.c_int
@@ -182,10 +182,11 @@ def energy_order(first, last, sigma):
     return order
 
 
-def join(L, bin_shift, seed, trace, lnW, sigma, r, mode=0):
+def join(L, bin_shift, seed, trace, lnW, sigma, r, mode=0, chain_offset=0):
     """Join one round.  trace: (p, M) array of E/4.  mode 0: detailed balance
     in chain order; 1: naive splice; 2: detailed balance with the chains in
-    energy order.  Returns (cut, H, retained, new_sigma)."""
+    energy order.  chain_offset: global index of the first chain (a block of a
+    split run).  Returns (cut, H, retained, new_sigma)."""
     tr = np.ascontiguousarray(trace, dtype=np.int32)
     p, M = tr.shape
     lnW = np.ascontiguousarray(lnW, dtype=np.float64)
@@ -197,7 +198,7 @@ def join(L, bin_shift, seed, trace, lnW, sigma, r, mode=0):
     if mode == 2:
         half = L * L // 2
         order = energy_order(tr[:, 0] + half, tr[:, M - 1] + half, sigma)
-    lib().orc_join(L, bin_shift, seed, p, M, _ptr(tr), _ptr(lnW), _ptr(sig), r, 1 if mode == 1 else 0,
+    lib().orc_join(L, bin_shift, seed, chain_offset, p, M, _ptr(tr), _ptr(lnW), _ptr(sig), r, 1 if mode == 1 else 0,
                    _ptr(order) if order is not None else None, _ptr(cut), _ptr(H), _ptr(ret))
     return cut, H, int(ret[0]), int(sig[0])
 
@@ -254,7 +255,8 @@ class Run:
         return tr, hist
 
     def join(self, trace, mode=0):
-        cut, H, ret, self.sigma = join(self.L, self.bin_shift, self.seed, trace, self.lnW, self.sigma, self.r, mode)
+        cut, H, ret, self.sigma = join(self.L, self.bin_shift, self.seed, trace, self.lnW, self.sigma, self.r, mode,
+                                       self.c0)
         self.r += 1
         self.H += H
         self.retained += ret

@@ -239,12 +239,14 @@ void orc_sweeps(int32_t L, uint32_t seed, int32_t bin_shift, uint32_t c, int8_t 
    order: NULL for the chains in index order, else the chain taken at each
    position (a permutation of 0..p-1, the energy ordering of Sec. 2's remark;
    see orc_energy_order).  The test of chain c's k-th configuration draws its
-   word from (round r, chain c, position k), whatever its place in the order.
+   word from (round r, chain c_off + c, position k), whatever its place in the
+   order: c_off is the global index of chain 0 when a run is split into blocks
+   of chains, each joined in turn from the seam the block before ended with.
    mode 0: detailed balance at the joints (the paper's method);
    mode 1: every chain kept whole (the naive splice compared in Sec. 5). */
-void orc_join(int32_t L, int32_t bin_shift, uint32_t seed, int32_t p, int64_t M, const int32_t *trace,
-              const double *lnW, int32_t *sigma_io, uint32_t r, int32_t mode, const int32_t *order, int32_t *cut,
-              int64_t *H, int64_t *retained)
+void orc_join(int32_t L, int32_t bin_shift, uint32_t seed, uint32_t c_off, int32_t p, int64_t M,
+              const int32_t *trace, const double *lnW, int32_t *sigma_io, uint32_t r, int32_t mode, const int32_t *order,
+              int32_t *cut, int64_t *H, int64_t *retained)
 {
     int N = L * L;
     int32_t sigma = *sigma_io;
@@ -258,7 +260,7 @@ void orc_join(int32_t L, int32_t bin_shift, uint32_t seed, int32_t p, int64_t M,
             for (int64_t k = 0; k < M; ++k) {
                 int32_t mk = tr[k] + N / 2;
                 double d = lnW[mk >> bin_shift] - lnW[sigma >> bin_shift];
-                uint32_t u = orc_uniform(seed, L, 2u, r, (uint32_t)c, (uint32_t)k);
+                uint32_t u = orc_uniform(seed, L, 2u, r, c_off + (uint32_t)c, (uint32_t)k);
                 if (orc_accept(orc_threshold(d), u)) {
                     kstar = k;
                     break;

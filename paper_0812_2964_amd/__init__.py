@@ -26,7 +26,7 @@ EXPORTED = ["mc_create", "mc_destroy", "mc_n_bins", "mc_trace_elem_bytes", "mc_l
             "mc_graph_create", "mc_graph_launch", "mc_graph_destroy", "mc_sync", "mc_last_error",
             "mc_mlp_n_params", "mc_mlp_workspace_bytes", "mc_mlp_init", "mc_mlp_forward", "mc_mlp_loss_grad",
             "mc_mlp_train", "mc_mlp_targets", "mc_mlp_predict_weights", "mc_thermo", "mc_iterate_topup",
-            "mc_get_state", "mc_set_state"]
+            "mc_get_state", "mc_set_state", "mc_set_seam"]
 
 
 class MCError(RuntimeError):
@@ -37,7 +37,7 @@ class MCError(RuntimeError):
 
 class _Size(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32), ("n_chains", ctypes.c_int32), ("seed", ctypes.c_uint32),
-                ("bin_shift", ctypes.c_int32)]
+                ("bin_shift", ctypes.c_int32), ("chain_offset", ctypes.c_uint32)]
 
 
 _lib = None
@@ -66,6 +66,7 @@ def lib():
     L.mc_update_weights.argtypes = [p, i32, p, p, p, p]
     L.mc_iterate_topup.argtypes = [p, i64, i64, i32, p, p, p, i32, p, p, p, p]
     L.mc_get_state.argtypes = [p, p, ctypes.POINTER(ctypes.c_size_t)]
+    L.mc_set_seam.argtypes = [p, i32, i32]
     L.mc_set_state.argtypes = [p, p, ctypes.c_size_t]
     L.mc_get_levels.argtypes = [p, i32, p]
     L.mc_get_lattice.argtypes = [p, i32, i32, p, i32]
@@ -119,14 +120,16 @@ def _dev_ptr(t, dtype, numel=None, name="tensor"):
 class Context:
     """Chains of one or more lattice sizes on the current GPU (mc_create).
 
-    sizes: list of (L, n_chains, seed, bin_shift) tuples.
+    sizes: list of (L, n_chains, seed, bin_shift) or (L, n_chains, seed,
+    bin_shift, chain_offset) tuples.
     """
 
     def __init__(self, sizes, stream=None):
         import torch
 
         self.sizes = [tuple(s) for s in sizes]
-        arr = (_Size * len(sizes))(*[_Size(int(L), int(p), int(seed), int(bs)) for (L, p, seed, bs) in sizes])
+        arr = (_Size * len(sizes))(*[_Size(int(s[0]), int(s[1]), int(s[2]), int(s[3]), int(s[4]) if len(s) > 4 else 0)
+                                     for s in self.sizes])
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = ctypes.c_void_p()
         _check(lib().mc_create(arr, len(sizes), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
@@ -277,6 +280,10 @@ class Context:
         sw = ctypes.c_uint32()
         _check(lib().mc_get_counters(self._h, i, ctypes.byref(seam), ctypes.byref(rnd), ctypes.byref(sw)))
         return seam.value, rnd.value, sw.value
+
+    def set_seam(self, seam, i=0):
+        """The seam the next joint of size i starts from (mc_set_seam)."""
+        _check(lib().mc_set_seam(self._h, i, int(seam)))
 
     def weights(self, i=0):
         w = np.zeros(self.n_bins(i), dtype=np.float64)

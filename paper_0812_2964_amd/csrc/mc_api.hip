@@ -389,14 +389,14 @@ static uint32_t crc32_of(const unsigned char *p, size_t n) {
 }
 
 // State blob: a 24-byte header {"MCS1", version, crc, n_sizes, total bytes}
-// and per size {L, n_chains, seed, bin_shift, W, n_bins, pending, last_M,
+// and per size {L, n_chains, seed, bin_shift, W, n_bins, chain_offset, pending, last_M,
 // the Ctl counters field by field, lattice words, levels, ln w}, all
 // little-endian; the CRC-32 covers the whole blob with its crc field zero.
 constexpr uint32_t kStateVersion = 1;
 constexpr size_t kStateHeader = 24;
 
 static size_t state_size_of(const SizeDev &d) {
-    return 6 * 4 + 2 * 8 + (4 * 4 + 2 * 8 + 2 * 4) + (size_t)d.L * d.W * d.P * 4 + (size_t)d.P * 4 +
+    return 7 * 4 + 2 * 8 + (4 * 4 + 2 * 8 + 2 * 4) + (size_t)d.L * d.W * d.P * 4 + (size_t)d.P * 4 +
            (size_t)d.n_bins * 8;
 }
 
@@ -416,6 +416,8 @@ mc_status mc_create(const mc_size *sizes, int32_t n_sizes, void *hip_stream, mc_
         if (c.n_chains < 1 || c.n_chains > (1 << 20))
             return fail(MC_EINVAL, "size %d: n_chains=%d must be 1..2^20", i, c.n_chains);
         if (c.bin_shift < 0 || c.bin_shift > 1) return fail(MC_EINVAL, "size %d: bin_shift must be 0 or 1", i);
+        if ((uint64_t)c.chain_offset + (uint64_t)c.n_chains > 0x100000000ull)
+            return fail(MC_EINVAL, "size %d: chain_offset + n_chains must not exceed 2^32", i);
     }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
@@ -447,6 +449,7 @@ mc_status mc_create(const mc_size *sizes, int32_t n_sizes, void *hip_stream, mc_
         d.bin_shift = h.cfg.bin_shift;
         d.n_bins = (d.N >> d.bin_shift) + 1;
         d.seed = h.cfg.seed;
+        d.c_off = h.cfg.chain_offset;
         d.trace_bytes = (d.L <= 254) ? 2 : 4;
         d.tab_r = d.bin_shift == 0 ? 2 : 1;
         const size_t lat_b = (size_t)d.L * d.W * d.P * 4;
@@ -701,6 +704,20 @@ mc_status mc_get_counters(mc_ctx *ctx, int32_t i, int32_t *seam, uint32_t *round
     return MC_OK;
 }
 
+mc_status mc_set_seam(mc_ctx *ctx, int32_t i, int32_t seam) {
+    mc_status st = check_size(ctx, i);
+    if (st != MC_OK) return st;
+    HostSize &h = ctx->sizes[i];
+    if (seam < -1 || seam > h.dev.N) return fail(MC_EINVAL, "seam=%d must be -1..%d", seam, h.dev.N);
+    Ctl c{};
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(&c, h.dev.ctl, sizeof c, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+    c.sigma = seam;
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(h.dev.ctl, &c, sizeof c, hipMemcpyHostToDevice, ctx->stream));
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+    return MC_OK;
+}
+
 mc_status mc_sync(mc_ctx *ctx) {
     mc_status st = check_ctx(ctx);
     if (st != MC_OK) return st;
@@ -747,7 +764,7 @@ mc_status mc_get_state(mc_ctx *ctx, void *buf, size_t *len) {
         Ctl c{};
         HIP_OR_FAIL(ctx, hipMemcpyAsync(&c, d.ctl, sizeof c, hipMemcpyDeviceToHost, ctx->stream));
         const size_t lat_b = (size_t)d.L * d.W * d.P * 4;
-        const size_t base = at + 6 * 4 + 2 * 8 + (4 * 4 + 2 * 8 + 2 * 4);
+        const size_t base = at + 7 * 4 + 2 * 8 + (4 * 4 + 2 * 8 + 2 * 4);
         HIP_OR_FAIL(ctx, hipMemcpyAsync(o + base, d.lat, lat_b, hipMemcpyDeviceToHost, ctx->stream));
         HIP_OR_FAIL(ctx, hipMemcpyAsync(o + base + lat_b, d.lev, (size_t)d.P * 4, hipMemcpyDeviceToHost, ctx->stream));
         HIP_OR_FAIL(ctx, hipMemcpyAsync(o + base + lat_b + (size_t)d.P * 4, d.lnW, (size_t)d.n_bins * 8,
@@ -759,6 +776,7 @@ mc_status mc_get_state(mc_ctx *ctx, void *buf, size_t *len) {
         put32((uint32_t)d.bin_shift);
         put32((uint32_t)d.W);
         put32((uint32_t)d.n_bins);
+        put32(d.c_off);
         put64((uint64_t)h.pending);
         put64((uint64_t)h.last_M);
         put32(c.g);
@@ -810,9 +828,10 @@ mc_status mc_set_state(mc_ctx *ctx, const void *buf, size_t len) {
     };
     for (const auto &h : ctx->sizes) {
         const SizeDev &d = h.dev;
-        if (at + 24 > len) return fail(MC_ECORRUPT, "state too short");
+        if (at + 28 > len) return fail(MC_ECORRUPT, "state too short");
         if ((int)get32(at) != d.L || (int)get32(at + 4) != d.P || get32(at + 8) != d.seed ||
-            (int)get32(at + 12) != d.bin_shift || (int)get32(at + 16) != d.W || (int)get32(at + 20) != d.n_bins)
+            (int)get32(at + 12) != d.bin_shift || (int)get32(at + 16) != d.W || (int)get32(at + 20) != d.n_bins ||
+            get32(at + 24) != d.c_off)
             return fail(MC_EINVAL, "the state's sizes differ from the context's");
         if (at + state_size_of(d) > len) return fail(MC_ECORRUPT, "state too short");
         const size_t lnw = at + state_size_of(d) - (size_t)d.n_bins * 8;
@@ -829,15 +848,15 @@ mc_status mc_set_state(mc_ctx *ctx, const void *buf, size_t len) {
     for (auto &h : ctx->sizes) {
         SizeDev &d = h.dev;
         Ctl c{};
-        c.g = get32(at + 40);
-        c.r = get32(at + 44);
-        c.sigma = (int32_t)get32(at + 48);
-        c.flat = (int32_t)get32(at + 52);
-        c.retained = (int64_t)get64(at + 56);
-        c.retained_last = (int64_t)get64(at + 64);
-        c.iter = (int32_t)get32(at + 72);
-        c.flat_iter = (int32_t)get32(at + 76);
-        const size_t base = at + 80;
+        c.g = get32(at + 44);
+        c.r = get32(at + 48);
+        c.sigma = (int32_t)get32(at + 52);
+        c.flat = (int32_t)get32(at + 56);
+        c.retained = (int64_t)get64(at + 60);
+        c.retained_last = (int64_t)get64(at + 68);
+        c.iter = (int32_t)get32(at + 76);
+        c.flat_iter = (int32_t)get32(at + 80);
+        const size_t base = at + 84;
         const size_t lat_b = (size_t)d.L * d.W * d.P * 4;
         HIP_OR_FAIL(ctx, hipMemcpyAsync(d.ctl, &c, sizeof c, hipMemcpyHostToDevice, ctx->stream));
         HIP_OR_FAIL(ctx, hipMemcpyAsync(d.lat, b + base, lat_b, hipMemcpyHostToDevice, ctx->stream));
@@ -847,8 +866,8 @@ mc_status mc_set_state(mc_ctx *ctx, const void *buf, size_t len) {
         HIP_OR_FAIL(ctx, hipMemsetAsync(d.hist64, 0, (size_t)d.n_bins * 8, ctx->stream));
         HIP_OR_FAIL(ctx, launch_tabulate(d, ctx->stream));
         HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
-        h.pending = (int64_t)get64(at + 24);
-        h.last_M = (int64_t)get64(at + 32);
+        h.pending = (int64_t)get64(at + 28);
+        h.last_M = (int64_t)get64(at + 36);
         at += state_size_of(d);
     }
     return MC_OK;

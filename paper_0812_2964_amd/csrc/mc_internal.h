@@ -24,6 +24,7 @@ struct SizeDev {
     int32_t P;              // chains
     int32_t bin_shift, n_bins;
     uint32_t seed;
+    uint32_t c_off;         // global index of chain 0 (the random words are keyed by the global index)
     int32_t trace_bytes;    // 2 (int16) or 4 (int32)
     uint32_t *lat;          // [L*W][P] chain-interleaved bit-packed rows
     int32_t *lev;           // [P] current level of each chain

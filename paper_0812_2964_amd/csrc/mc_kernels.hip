@@ -30,7 +30,7 @@ __global__ void k_init(SizeDev s) {
                 const int x = w * 32 + b;
                 if (x >= L) break;
                 const uint32_t j = (uint32_t)(y * L + x);
-                const uint4 blk = philox10(make_uint4(j >> 2, 0u, (uint32_t)c, kDomInit), s.seed, (uint32_t)L);
+                const uint4 blk = philox10(make_uint4(j >> 2, 0u, (uint32_t)c + s.c_off, kDomInit), s.seed, (uint32_t)L);
                 word |= (word_of(blk, j & 3u) >> 31) << b;
             }
             s.lat[(size_t)(y * W + w) * s.P + c] = word;
@@ -244,7 +244,7 @@ __device__ __forceinline__ void sweep_tile_lds(const SizeDev &s, int c0, int cpb
             Row<L> cur = load(0);
             Row<L> dn = load(1);
             for (int y = 0; y < L; ++y) {
-                sweep_row<L>((uint32_t)y, g, (uint32_t)c, k0, k1, cur, up, dn, mi, tab);
+                sweep_row<L>((uint32_t)y, g, (uint32_t)c + s.c_off, k0, k1, cur, up, dn, mi, tab);
                 store(y, cur);
                 up = cur;
                 cur = dn;
@@ -442,12 +442,13 @@ __device__ __forceinline__ void pc_row(Row<L> &cur, const Row<L> &up, const Row<
 }
 
 // Random words of one chunk: rows y0 .. y0+R-1 of sweep g for every chain of
-// the block, item it = rq * cpb + l (word group rq of the chunk, chain l).
+// the block, item it = rq * cpb + l (word group rq of the chunk, chain l; the
+// words are those of global chain cg0 + l).
 // Producer thread pt of np takes items pt, pt + np, ..., two independent
 // Philox calls at a time; lanes whose chain is beyond P write words that are
 // never read.
 template <int L>
-__device__ __forceinline__ void pc_produce(uint4 *ub, int R, uint32_t y0, uint32_t g, int c0, int cpb,
+__device__ __forceinline__ void pc_produce(uint4 *ub, int R, uint32_t y0, uint32_t g, uint32_t cg0, int cpb,
                                            uint32_t k0, uint32_t k1, int pt, int np) {
     constexpr int NQ = L / 4;
     const int items = R * NQ * cpb;
@@ -465,8 +466,8 @@ __device__ __forceinline__ void pc_produce(uint4 *ub, int R, uint32_t y0, uint32
     for (int it = pt; it < items; it += 2 * np) {
         int l1 = l, rq1 = rq;
         step(l1, rq1);
-        const uint4 v0 = philox10(make_uint4(ctr0 + (uint32_t)rq, g, (uint32_t)(c0 + l), kDomSweep), k0, k1);
-        const uint4 v1 = philox10(make_uint4(ctr0 + (uint32_t)rq1, g, (uint32_t)(c0 + l1), kDomSweep), k0, k1);
+        const uint4 v0 = philox10(make_uint4(ctr0 + (uint32_t)rq, g, cg0 + (uint32_t)l, kDomSweep), k0, k1);
+        const uint4 v1 = philox10(make_uint4(ctr0 + (uint32_t)rq1, g, cg0 + (uint32_t)l1, kDomSweep), k0, k1);
         ub[it] = v0;
         if (it + np < items) ub[it + np] = v1;
         l = l1;
@@ -515,7 +516,7 @@ __device__ __forceinline__ void sweep_tile_pc(const SizeDev &s, int c0, int cpb,
     const int np = blockDim.x - 64, pt = threadIdx.x - 64;
     const int per_sweep = L / R;
     const int64_t n_chunks = M * per_sweep;
-    if (!consumer) pc_produce<L>(ubuf, R, 0u, g0, c0, cpb, k0, k1, pt, np);
+    if (!consumer) pc_produce<L>(ubuf, R, 0u, g0, (uint32_t)c0 + s.c_off, cpb, k0, k1, pt, np);
     __syncthreads();
 
     uint32_t mib = 0;
@@ -561,7 +562,7 @@ __device__ __forceinline__ void sweep_tile_pc(const SizeDev &s, int c0, int cpb,
         } else if (!consumer && i + 1 < n_chunks) {
             const int64_t k1s = (i + 1) / per_sweep;
             const int y1 = (int)(i + 1 - k1s * per_sweep) * R;
-            pc_produce<L>(ubuf + (size_t)((i + 1) & 1) * chunk_words, R, (uint32_t)y1, g0 + (uint32_t)k1s, c0, cpb,
+            pc_produce<L>(ubuf + (size_t)((i + 1) & 1) * chunk_words, R, (uint32_t)y1, g0 + (uint32_t)k1s, (uint32_t)c0 + s.c_off, cpb,
                           k0, k1, pt, np);
         }
         __syncthreads();
@@ -721,7 +722,7 @@ __device__ __forceinline__ void sweep_tile_pcq(const SizeDev &s, int c0, int cpb
     const int np = blockDim.x - 64, pt = threadIdx.x - 64;
     const int per_sweep = L / R;
     const int64_t n_chunks = M * per_sweep;
-    if (!consumer) pc_produce<L>(ubuf, R, 0u, g0, c0, cpb, k0, k1, pt, np);
+    if (!consumer) pc_produce<L>(ubuf, R, 0u, g0, (uint32_t)c0 + s.c_off, cpb, k0, k1, pt, np);
     __syncthreads();
 
     uint32_t mib = 0;
@@ -767,7 +768,7 @@ __device__ __forceinline__ void sweep_tile_pcq(const SizeDev &s, int c0, int cpb
         } else if (!consumer && i + 1 < n_chunks) {
             const int64_t k1s = (i + 1) / per_sweep;
             const int y1 = (int)(i + 1 - k1s * per_sweep) * R;
-            pc_produce<L>(ubuf + (size_t)((i + 1) & 1) * chunk_words, R, (uint32_t)y1, g0 + (uint32_t)k1s, c0, cpb,
+            pc_produce<L>(ubuf + (size_t)((i + 1) & 1) * chunk_words, R, (uint32_t)y1, g0 + (uint32_t)k1s, (uint32_t)c0 + s.c_off, cpb,
                           k0, k1, pt, np);
         }
         __syncthreads();
@@ -935,7 +936,7 @@ __device__ __forceinline__ void sweep_tile_big(const SizeDev &s, int c0, int cpb
     const int np = blockDim.x - 64, pt = threadIdx.x - 64;
     const int per_sweep = L / R;
     const int64_t n_chunks = M * per_sweep;
-    if (!consumer) pc_produce<L>(ubuf, R, 0u, g0, c0, cpb, k0, k1, pt, np);
+    if (!consumer) pc_produce<L>(ubuf, R, 0u, g0, (uint32_t)c0 + s.c_off, cpb, k0, k1, pt, np);
     __syncthreads();
 
     const uint32_t B0 = (TAB_LDS ? (uint32_t)(size_t)(lds_u32 *)(stab) : 0u) + 4u * (uint32_t)r;
@@ -967,7 +968,7 @@ __device__ __forceinline__ void sweep_tile_big(const SizeDev &s, int c0, int cpb
         } else if (!consumer && i + 1 < n_chunks) {
             const int64_t k1s = (i + 1) / per_sweep;
             const int y1 = (int)(i + 1 - k1s * per_sweep) * R;
-            pc_produce<L>(ubuf + (size_t)((i + 1) & 1) * chunk_words, R, (uint32_t)y1, g0 + (uint32_t)k1s, c0, cpb,
+            pc_produce<L>(ubuf + (size_t)((i + 1) & 1) * chunk_words, R, (uint32_t)y1, g0 + (uint32_t)k1s, (uint32_t)c0 + s.c_off, cpb,
                           k0, k1, pt, np);
         }
         __syncthreads();
@@ -1153,7 +1154,7 @@ __device__ __forceinline__ void sweep_tile_bigq(const SizeDev &s, int c0, int cp
     const int np = (int)blockDim.x - 64 * nc, pt = (int)threadIdx.x - 64 * nc;
     const int per_sweep = L / R;
     const int64_t n_chunks = M * per_sweep;
-    if (!consumer) pc_produce<L>(ubuf, R, 0u, g0, c0, cpb, k0, k1, pt, np);
+    if (!consumer) pc_produce<L>(ubuf, R, 0u, g0, (uint32_t)c0 + s.c_off, cpb, k0, k1, pt, np);
     __syncthreads();
 
     const uint32_t B0 = (TAB_LDS ? (uint32_t)(size_t)(lds_u32 *)(stab) : 0u) + 4u * (uint32_t)r;
@@ -1181,7 +1182,7 @@ __device__ __forceinline__ void sweep_tile_bigq(const SizeDev &s, int c0, int cp
         } else if (!consumer && i + 1 < n_chunks) {
             const int64_t k1s = (i + 1) / per_sweep;
             const int y1 = (int)(i + 1 - k1s * per_sweep) * R;
-            pc_produce<L>(ubuf + (size_t)((i + 1) & 1) * chunk_words, R, (uint32_t)y1, g0 + (uint32_t)k1s, c0, cpb,
+            pc_produce<L>(ubuf + (size_t)((i + 1) & 1) * chunk_words, R, (uint32_t)y1, g0 + (uint32_t)k1s, (uint32_t)c0 + s.c_off, cpb,
                           k0, k1, pt, np);
         }
         __syncthreads();
@@ -1225,7 +1226,7 @@ __global__ __launch_bounds__(64) void k_sweep_glb(SweepParams p) {
         Row<L> cur = load(0);
         Row<L> dn = load(1);
         for (int y = 0; y < L; ++y) {
-            sweep_row<L>((uint32_t)y, g, (uint32_t)c, k0, k1, cur, up, dn, mi, s.tab);
+            sweep_row<L>((uint32_t)y, g, (uint32_t)c + s.c_off, k0, k1, cur, up, dn, mi, s.tab);
             store(y, cur);
             up = cur;
             cur = dn;
@@ -1258,7 +1259,7 @@ __global__ __launch_bounds__(64) void k_sweep_generic(SweepParams p) {
         uint4 blk = make_uint4(0, 0, 0, 0);
         for (int j = 0; j < N; ++j) {
             if ((j & 3) == 0)
-                blk = philox10(make_uint4((uint32_t)j >> 2, g, (uint32_t)c, kDomSweep), s.seed, (uint32_t)L);
+                blk = philox10(make_uint4((uint32_t)j >> 2, g, (uint32_t)c + s.c_off, kDomSweep), s.seed, (uint32_t)L);
             const uint32_t u = word_of(blk, (uint32_t)j & 3u);
             const int x = j % L, y = j / L;
             const uint32_t sv = spin(y, x);
@@ -1625,7 +1626,7 @@ __device__ int join_scan(const SizeDev &s, const TT *row, int64_t M, int sigma, 
         if (k < M) {
             const int mk = min(max((int)row[k] + half, 0), s.N);  // traces come from the sweeps; clamp anyway
             const uint32_t t = tau_of(s.lnW[mk >> s.bin_shift] - ws);
-            const uint4 blk = philox10(make_uint4((uint32_t)k >> 2, r, i, kDomJoin), s.seed, (uint32_t)s.L);
+            const uint4 blk = philox10(make_uint4((uint32_t)k >> 2, r, i + s.c_off, kDomJoin), s.seed, (uint32_t)s.L);
             acc = word_of(blk, (uint32_t)k & 3u) <= t;
         }
         const unsigned long long bal = __ballot(acc);

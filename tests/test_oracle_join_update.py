@@ -150,3 +150,33 @@ def test_recursion_converges_to_exact_dos_L4_levels():
     reach = g > 0
     d = (R.lnW + np.log(np.maximum(g, 1)))[reach]
     assert d.max() - d.min() < 0.15
+
+
+def test_blockwise_joint_equals_the_whole():
+    """A run split into two blocks of chains (chain offsets 0 and p/2) makes
+    the same traces as the whole run, and joining the blocks in turn, the
+    second from the seam the first ended with, keeps exactly what one joint
+    over all chains keeps -- the exchange a run split over several GPUs
+    needs.  Three rounds, a non-trivial weight, detailed balance and the
+    naive splice."""
+    L, p, M, bs = 8, 12, 25, 1
+    # a weight and round count for which starting a block from any other seam
+    # (its own end of the round before, say) changes the cut points
+    rng = np.random.default_rng(13)
+    lnW = rng.normal(0, 3.0, O.n_bins(L, bs))
+    for mode in (0, 1):
+        whole = O.Run(L, p, seed=4, bin_shift=bs, lnW=lnW)
+        parts = [O.Run(L, p // 2, seed=4, bin_shift=bs, lnW=lnW, chain_offset=o) for o in (0, p // 2)]
+        for _ in range(3):
+            tr, _ = whole.run(M)
+            cut, H = whole.join(tr, mode)
+            trs = [q.run(M)[0] for q in parts]
+            assert np.array_equal(np.concatenate(trs), tr)
+            parts[0].sigma = parts[1].sigma  # each round starts where the last block ended (step 4)
+            c0, H0 = parts[0].join(trs[0], mode)
+            parts[1].sigma = parts[0].sigma
+            c1, H1 = parts[1].join(trs[1], mode)
+            assert np.array_equal(np.concatenate([c0, c1]), cut)
+            assert np.array_equal(H0 + H1, H)
+            assert parts[1].sigma == whole.sigma
+        assert parts[0].retained + parts[1].retained == whole.retained
