@@ -603,10 +603,11 @@ __device__ __forceinline__ uint32_t quad_bcast(uint32_t v) {
 }
 
 // One row of the quad consumer.  hxm, hym: all ones in lanes that assume site
-// x (x+1) of pair p accepted.
+// x (x+1) of pair p accepted; jq: the lane's place in its quad.
 template <int L>
 __device__ __forceinline__ void pcq_row(Row<L> &cur, const Row<L> &up, const Row<L> &dn, uint32_t &mib,
-                                        uint32_t pair_addr, const uint4 *urow, int cpb, uint32_t hxm, uint32_t hym) {
+                                        uint32_t pair_addr, const uint4 *urow, int cpb, uint32_t hxm, uint32_t hym,
+                                        uint32_t jq) {
     static_assert(L >= 8 && L % 4 == 0, "two pairs per step, site 0 decided before the last step");
     constexpr int W = (L + 31) / 32;
     constexpr int wl = (L - 1) >> 5, bl = (L - 1) & 31;
@@ -625,11 +626,25 @@ __device__ __forceinline__ void pcq_row(Row<L> &cur, const Row<L> &up, const Row
 #pragma unroll
     for (int w = 0; w < W; ++w) hs.w[w] = (hb.w[w] << 1) | (w > 0 ? hb.w[w - 1] >> 31 : 0u);
     hs.w[0] |= (hb.w[wl] >> bl) & 1u;
+    // The table addresses of the row's pairs, shared out over the quad: lane jq
+    // holds those of pairs 4k + jq (k = 0 .. NK-1); a step takes the ones it
+    // needs from their lanes with a DPP broadcast.
+    constexpr int NK = (L / 2 + 3) / 4;
+    uint32_t own[NK];
+    auto addr_of = [&](int k) {
+        const int w = (8 * k) >> 5;
+        const uint32_t b = (uint32_t)((8 * k) & 31) + 2u * jq;
+        const uint32_t idx = __builtin_amdgcn_ubfe(P0.w[w], b, 2) | (__builtin_amdgcn_ubfe(P1.w[w], b, 2) << 2) |
+                             (__builtin_amdgcn_ubfe(hs.w[w], b, 2) << 4);
+        return pair_addr + idx * 16u;
+    };
+#pragma unroll
+    for (int k = 0; k < NK; ++k) own[k] = addr_of(k);
     auto entry = [&](int p) {
-        const int w = (2 * p) >> 5, b = (2 * p) & 31;
-        const uint32_t idx =
-            ((P0.w[w] >> b) & 3u) | (((P1.w[w] >> b) & 3u) << 2) | (((hs.w[w] >> b) & 3u) << 4);
-        return lds_load96(pair_addr + idx * 16u);
+        const uint32_t v = own[p >> 2];
+        const uint32_t a = (p & 3) == 0 ? quad_bcast<0x00>(v) : (p & 3) == 1 ? quad_bcast<0x55>(v)
+                         : (p & 3) == 2 ? quad_bcast<0xAA>(v) : quad_bcast<0xFF>(v);
+        return lds_load96(a);
     };
     bool aprev = false;
     uint4 n0 = entry(0), n1 = entry(1);
@@ -641,6 +656,7 @@ __device__ __forceinline__ void pcq_row(Row<L> &cur, const Row<L> &up, const Row
             const uint32_t hl = hb.w[wl] ^ ((fl.w[0] & 1u) << bl);
             P0.w[wl] = __builtin_amdgcn_bitop3_b32(xu.w[wl], xd.w[wl], hl, 0x96);
             P1.w[wl] = __builtin_amdgcn_bitop3_b32(xu.w[wl], xd.w[wl], hl, 0xE8);
+            own[(L / 2 - 1) >> 2] = addr_of((L / 2 - 1) >> 2);
         }
         const uint4 ea = n0;
         // with two steps per row the last pair's entry is read after the fix above
@@ -748,7 +764,8 @@ __device__ __forceinline__ void sweep_tile_pcq(const SizeDev &s, int c0, int cpb
             }
             for (int r = 0; r < R; ++r) {
                 const int y = y0 + r;
-                pcq_row<L>(cur, up, dn, mib, pair_addr, ub + (size_t)r * (L / 4) * cpb + cl, cpb, hxm, hym);
+                pcq_row<L>(cur, up, dn, mib, pair_addr, ub + (size_t)r * (L / 4) * cpb + cl, cpb, hxm, hym,
+                           (uint32_t)j);
                 // the four lanes of the quad hold the same row
 #pragma unroll
                 for (int w = 0; w < W; ++w) slat[(y * W + w) * cpb + cl] = cur.w[w];
@@ -1070,6 +1087,8 @@ __device__ __forceinline__ void bigq_row(uint32_t *lat, size_t P, int c, int y, 
         const uint32_t hs = (hb << 1) | carry;  // left bonds
         carry = hb >> 31;
         const uint4 *uw4 = urow + (size_t)w * 8 * cpb;
+        // (sharing these indices over the quad, as pcq_row does, was measured
+        // slower here: 124 against 124 cycles at L = 128, 141 against 127 at 256)
         auto entry = [&](int p) {
             const uint32_t idx = ((P0 >> (2 * p)) & 3u) | (((P1 >> (2 * p)) & 3u) << 2) | (((hs >> (2 * p)) & 3u) << 4);
             return lds_load96(pair_addr + idx * 16u);

@@ -54,3 +54,33 @@ def test_split_run_equals_whole_run(L, P, bs):
             assert np.array_equal(wb.view(np.uint64), ww.view(np.uint64)) and fb == fw, it
     for c in [whole] + blocks:
         c.close()
+
+
+@pytest.mark.parametrize("sizes", [[(32, 300, 2, 1)], [(128, 70, 2, 1)], [(16, 100, 2, 1), (64, 50, 2, 1)]])
+def test_runs_are_deterministic(sizes):
+    """The same run twice in fresh contexts gives the same bits: traces, cuts,
+    joined histograms (LDS histograms merged with atomics, the speculative
+    joint) and ln w, for the quad kernels of both lattice ranges and the
+    batched launch."""
+    import paper_0812_2964_amd as mc
+
+    def run():
+        ctx = mc.Context(sizes)
+        out = []
+        for _ in range(2):
+            trs = [ctx.new_trace(40, i) for i in range(len(sizes))]
+            hs = [ctx.new_hist(i) for i in range(len(sizes))]
+            cuts = [ctx.new_cut(i) for i in range(len(sizes))]
+            ctx.run_chains(40, trs, hs)
+            for i in range(len(sizes)):
+                ctx.join(trs[i], cuts[i], hs[i], i=i)
+                joined = hs[i].cpu().numpy().copy()
+                w, _, _ = ctx.update_weights(hs[i], i=i)
+                out.append((trs[i].cpu().numpy(), cuts[i].cpu().numpy(), joined, w.view(np.uint64)))
+        ctx.close()
+        return out
+
+    a, b = run(), run()
+    for xa, xb in zip(a, b):
+        for ya, yb in zip(xa, xb):
+            assert np.array_equal(ya, yb)
