@@ -603,11 +603,14 @@ __device__ __forceinline__ uint32_t quad_bcast(uint32_t v) {
 }
 
 // One row of the quad consumer.  hxm, hym: all ones in lanes that assume site
-// x (x+1) of pair p accepted; jq: the lane's place in its quad.
+// x (x+1) of pair p accepted; jq: the lane's place in its quad; hf0 / hf1: its
+// result flags (jq, its assumed outcome of pair p, in bits 28-29, plus bit 30
+// when pair p+1's first site is accepted), so that the word selected for the
+// quad carries the step's four flips in bits 28-31.
 template <int L>
 __device__ __forceinline__ void pcq_row(Row<L> &cur, const Row<L> &up, const Row<L> &dn, uint32_t &mib,
                                         uint32_t pair_addr, const uint4 *urow, int cpb, uint32_t hxm, uint32_t hym,
-                                        uint32_t jq) {
+                                        uint32_t jq, uint32_t hf0, uint32_t hf1) {
     static_assert(L >= 8 && L % 4 == 0, "two pairs per step, site 0 decided before the last step");
     constexpr int W = (L + 31) / 32;
     constexpr int wl = (L - 1) >> 5, bl = (L - 1) & 31;
@@ -686,8 +689,9 @@ __device__ __forceinline__ void pcq_row(Row<L> &cur, const Row<L> &up, const Row
         const uint32_t nA = mh + (uint32_t)(bx ? sbyte(Vq, 3) : sbyte(eb.x, 3));
         const uint32_t nB = mh + (uint32_t)(bx ? sbyte(Vq, 2) : 0);
         const bool bx1 = u4.w <= qn;
-        // result of the assumption: next state, and the two decisions in bits 30, 31
-        const uint32_t res = (bx1 ? nA : nB) | (bx ? 1u << 30 : 0u) | (bx1 ? 1u << 31 : 0u);
+        // result of the assumption: next state, the assumed outcome of pair p
+        // in bits 28-29 and the two decisions of pair p+1 in bits 30, 31
+        const uint32_t res = (bx1 ? nA : nB) | (bx ? hf1 : hf0) | (bx1 ? 1u << 31 : 0u);
         const uint32_t r0 = quad_bcast<0x00>(res), r1 = quad_bcast<0x55>(res);
         const uint32_t r2 = quad_bcast<0xAA>(res), r3 = quad_bcast<0xFF>(res);
         const bool ax = u4.x <= tx;
@@ -695,8 +699,9 @@ __device__ __forceinline__ void pcq_row(Row<L> &cur, const Row<L> &up, const Row
         const uint32_t rA = ax ? r3 : r2, rB = ax ? r1 : r0;
         const bool ax1 = u4.y <= tn;
         const uint32_t sel = ax1 ? rA : rB;
-        mib = sel & 0x3FFFFFFFu;
-        fl.w[w] |= (ax ? 1u << b : 0u) | (ax1 ? 2u << b : 0u) | ((sel >> 30) << (b + 2));
+        // the selected lane assumed the true outcome: bits 28-31 are the step's four flips
+        mib = sel & 0x0FFFFFFFu;
+        fl.w[w] |= (sel >> 28) << b;
         aprev = (sel >> 31) != 0u;
     }
 #pragma unroll
@@ -725,6 +730,7 @@ __device__ __forceinline__ void sweep_tile_pcq(const SizeDev &s, int c0, int cpb
     const bool active = consumer && cl < cpb && c < s.P;
     const bool lead = active && j == 0;  // one lane per chain for the global writes and atomics
     const uint32_t hxm = 0u - (uint32_t)(j & 1), hym = 0u - (uint32_t)((j >> 1) & 1);
+    const uint32_t hf0 = (uint32_t)j << 28, hf1 = hf0 | (1u << 30);
     const uint32_t k0 = s.seed, k1 = (uint32_t)L;
     const uint32_t g0 = s.ctl->g;
     for (int i = threadIdx.x; i < (N + 1) * 5; i += blockDim.x) {
@@ -765,7 +771,7 @@ __device__ __forceinline__ void sweep_tile_pcq(const SizeDev &s, int c0, int cpb
             for (int r = 0; r < R; ++r) {
                 const int y = y0 + r;
                 pcq_row<L>(cur, up, dn, mib, pair_addr, ub + (size_t)r * (L / 4) * cpb + cl, cpb, hxm, hym,
-                           (uint32_t)j);
+                           (uint32_t)j, hf0, hf1);
                 // the four lanes of the quad hold the same row
 #pragma unroll
                 for (int w = 0; w < W; ++w) slat[(y * W + w) * cpb + cl] = cur.w[w];
