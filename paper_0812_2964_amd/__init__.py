@@ -49,8 +49,7 @@ def lib():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise RuntimeError("libmcgpu.so is not built: run __graft_entry__.build() or "
-                           "python paper_0812_2964_amd/build.py")
+        raise RuntimeError("libmcgpu.so is not built: run python -m paper_0812_2964_amd.build")
     import torch  # noqa: F401  (loads the HIP runtime the library links against)
 
     L = ctypes.CDLL(LIB_PATH)
