@@ -249,7 +249,8 @@ mc_status mc_get_progress(mc_ctx *ctx, int32_t size_idx, int32_t *updates, int32
      0  lattice and per-level thresholds in LDS, one wave
      1  lattice in LDS, thresholds read from global memory, one wave
      2  lattice rows streamed from global memory, one wave
-     3  generic bit-by-bit kernel for L not among the compiled sizes
+     3  generic bit-by-bit kernel for L not among the compiled sizes (4, 8,
+        12, 16, 20, 24, 32, 40, 48, 64, 100, 128, 256)
      4  as 0, random words made by three producer waves of the workgroup, two
         sites decided per threshold read (L <= 64)
      5  L = 128, 256: lattice rows streamed from global memory one word at a
@@ -258,13 +259,13 @@ mc_status mc_get_progress(mc_ctx *ctx, int32_t size_idx, int32_t *updates, int32
      7  as 4 with four lanes per chain: each step decides four sites, the
         second pair under each of the four outcomes of the first
         (8 <= L <= 64, at most 16 chains per workgroup)
-     8  as 5 with four lanes per chain as in 7 (L = 128, 256, at most 32
+     8  as 5 with four lanes per chain as in 7 (L = 100, 128, 256, at most 32
         chains per workgroup: up to two consumer waves of 16 chains)
      9  as 8 with the per-bin thresholds read from global memory.
    By default 8 <= L <= 64 run kind 7 with 16 chains per workgroup, and
-   L = 128, 256 kind 8 (else 9) with 16 chains per workgroup, or 32 when there
+   L = 100, 128, 256 kind 8 (else 9) with 16 chains per workgroup, or 32 when there
    are more chains than 16 per compute unit.  mc_set_chains_per_block picks
-   kind 7 (L <= 64) or 8 / 9 (L >= 128) where the chains per workgroup allow
+   kind 7 (L <= 64) or 8 / 9 (L >= 100) where the chains per workgroup allow
    it (at most 16, resp. 32), else kind 4 or 5 / 6.
    mc_autotune: times probe_sweeps sweeps of every size on copies of the chain
    state for 16, 32 and 64 chains per workgroup, with the producer/consumer

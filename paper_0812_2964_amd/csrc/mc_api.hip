@@ -110,7 +110,7 @@ void free_size(SizeDev &d) {
 // quad-speculative kernel; otherwise the producer/consumer pair kernel with
 // the most chains per workgroup that fits, then the one-wave kernels.
 SizePlan default_plan(const SizeDev &d, int n_cu) {
-    if (d.L >= 128) {
+    if (d.L > 64) {
         const int cpb = (int64_t)d.P > 16ll * n_cu ? 32 : 16;
         SizePlan q = plan_sweeps(d, cpb, true);
         if (q.kind == kSweepBigQ || q.kind == kSweepBigQGlb) return q;

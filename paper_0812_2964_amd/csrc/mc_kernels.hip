@@ -1068,12 +1068,14 @@ template <int L, bool TAB_LDS>
 __device__ __forceinline__ void bigq_row(uint32_t *lat, size_t P, int c, int y, int &m, int bs, uint32_t B0, int sB,
                                          const uint32_t *tabc, uint32_t pair_addr, const uint4 *urow, int cpb,
                                          uint32_t hym, uint32_t sel_h, uint32_t f0, uint32_t f1) {
-    constexpr int W = L / 32;
+    static_assert(L % 4 == 0 && L > 64, "steps of four sites; at least three words per row");
+    constexpr int W = (L + 31) / 32;
+    constexpr int NB = L - 32 * (W - 1);  // sites in the last word (32 unless L % 32 != 0)
     const int yu = y == 0 ? L - 1 : y - 1, yd = y + 1 == L ? 0 : y + 1;
     auto word = [&](int yy, int w) { return lat + (size_t)(yy * W + w) * P + c; };
     uint32_t cn = *word(y, 0), un = *word(yu, 0), dn = *word(yd, 0), cnn = *word(y, 1);
     // bond (L-1, 0) at row start: the left bond of site 0
-    uint32_t carry = ((*word(y, W - 1) >> 31) ^ cn) & 1u;
+    uint32_t carry = ((*word(y, W - 1) >> (NB - 1)) ^ cn) & 1u;
     uint32_t c0new = 0u;
     bool aprev = false;
     for (int w = 0; w < W; ++w) {
@@ -1087,11 +1089,14 @@ __device__ __forceinline__ void bigq_row(uint32_t *lat, size_t P, int c, int y, 
             dn = *word(yd, w + 1);
             if (w + 2 < W) cnn = *word(y, w + 2);
         }
-        const uint32_t xu = cw ^ uw, xd = cw ^ dw, hb = cw ^ ((cw >> 1) | (cw1 << 31));
+        // the right neighbour of the word's last site: bit 0 of the next word, or
+        // for the last word (NB sites) site 0 of the row
+        const int nb = w + 1 < W ? 32 : NB;
+        const uint32_t xu = cw ^ uw, xd = cw ^ dw, hb = cw ^ ((cw >> 1) | ((cw1 & 1u) << (nb - 1)));
         const uint32_t P0 = __builtin_amdgcn_bitop3_b32(xu, xd, hb, 0x96);
         const uint32_t P1 = __builtin_amdgcn_bitop3_b32(xu, xd, hb, 0xE8);
         const uint32_t hs = (hb << 1) | carry;  // left bonds
-        carry = hb >> 31;
+        carry = (hb >> 31) & 1u;  // (a partial word is the last one: its carry is not used)
         const uint4 *uw4 = urow + (size_t)w * 8 * cpb;
         // (sharing these indices over the quad, as pcq_row does, was measured
         // slower here: 124 against 124 cycles at L = 128, 141 against 127 at 256)
@@ -1101,11 +1106,13 @@ __device__ __forceinline__ void bigq_row(uint32_t *lat, size_t P, int c, int y, 
         };
         uint32_t fw = 0u;
         uint4 n0 = entry(0), n1 = entry(1);
+        const int nst = nb / 4;  // steps of four sites in this word
 #pragma unroll
         for (int st = 0; st < 8; ++st) {
+            if (st >= nst) break;
             const int p = 2 * st;
             const uint4 ea = n0, eb = n1;
-            if (st + 1 < 8) {
+            if (st + 1 < nst) {
                 n0 = entry(p + 2);
                 n1 = entry(p + 3);
             }
@@ -1317,11 +1324,13 @@ hipError_t launch_advance(const SizeDev &s, int64_t M, hipStream_t st) {
 // static LDS.
 constexpr size_t kLdsMax = 160 * 1024 - 256;
 
-static bool big_size(int L) { return L == 128 || L == 256; }
+static bool big_size(int L) { return L == 128 || L == 256; }      // one lane per chain (kinds 5, 6)
+static bool bigq_size(int L) { return L == 100 || L == 128 || L == 256; }  // quad streamed rows (kinds 8, 9)
 
 static bool compiled_size(int L) {
     switch (L) {
-    case 4: case 8: case 12: case 16: case 20: case 24: case 32: case 40: case 48: case 64: case 128: case 256:
+    case 4: case 8: case 12: case 16: case 20: case 24: case 32: case 40: case 48: case 64: case 100: case 128:
+    case 256:
         return true;
     default:
         return false;
@@ -1337,7 +1346,7 @@ SizePlan plan_sweeps(const SizeDev &s, int cpb, bool allow_pc) {
         p.cpb = 64;
         return p;
     }
-    if (allow_pc && big_size(s.L) && p.cpb <= kBigqMaxChains) {
+    if (allow_pc && bigq_size(s.L) && p.cpb <= kBigqMaxChains) {
         for (int pass = 0; pass < 2; ++pass) {
             const bool tab_lds = pass == 0;
             for (int R = 4; R >= 1; R /= 2) {
@@ -1421,11 +1430,13 @@ static hipError_t allow_lds(const void *kernel, size_t &allowed, size_t bytes) {
 template <int L>
 static hipError_t prepare_L(const SizePlan &p) {
     static size_t allowed_tab = 0, allowed_notab = 0, allowed_pc = 0, allowed_big = 0, allowed_bigg = 0;
-    if constexpr (L >= 128) {
-        static size_t allowed_bq = 0, allowed_bqg = 0;
+    if constexpr (L >= 128 && L % 32 == 0) {
         if (p.kind == kSweepBig) return allow_lds((const void *)k_sweep_big<L, true>, allowed_big, p.lds_bytes);
         if (p.kind == kSweepBigGlb)
             return allow_lds((const void *)k_sweep_big<L, false>, allowed_bigg, p.lds_bytes);
+    }
+    if constexpr (L > 64 && L % 4 == 0) {
+        static size_t allowed_bq = 0, allowed_bqg = 0;
         if (p.kind == kSweepBigQ) return allow_lds((const void *)k_sweep_bigq<L, true>, allowed_bq, p.lds_bytes);
         if (p.kind == kSweepBigQGlb)
             return allow_lds((const void *)k_sweep_bigq<L, false>, allowed_bqg, p.lds_bytes);
@@ -1444,14 +1455,20 @@ template <int L>
 static hipError_t launch_L(const SweepParams &p0, const SizePlan &pl, hipStream_t st) {
     SweepParams p = p0;
     const dim3 grid((p.s.P + pl.cpb - 1) / pl.cpb), block(64);
-    if constexpr (L >= 128) {
-        if (pl.kind == kSweepBig || pl.kind == kSweepBigGlb || pl.kind == kSweepBigQ || pl.kind == kSweepBigQGlb) {
+    if constexpr (L >= 128 && L % 32 == 0) {
+        if (pl.kind == kSweepBig || pl.kind == kSweepBigGlb) {
             PcParams q{p.s, p.M, p.trace, p.hist, pl.cpb, pl.R};
             if (pl.kind == kSweepBig)
                 hipLaunchKernelGGL((k_sweep_big<L, true>), grid, dim3(kPcThreads), pl.lds_bytes, st, q);
-            else if (pl.kind == kSweepBigGlb)
+            else
                 hipLaunchKernelGGL((k_sweep_big<L, false>), grid, dim3(kPcThreads), pl.lds_bytes, st, q);
-            else if (pl.kind == kSweepBigQ)
+            return hipGetLastError();
+        }
+    }
+    if constexpr (L > 64 && L % 4 == 0) {
+        if (pl.kind == kSweepBigQ || pl.kind == kSweepBigQGlb) {
+            PcParams q{p.s, p.M, p.trace, p.hist, pl.cpb, pl.R};
+            if (pl.kind == kSweepBigQ)
                 hipLaunchKernelGGL((k_sweep_bigq<L, true>), grid, dim3(kPcThreads), pl.lds_bytes, st, q);
             else
                 hipLaunchKernelGGL((k_sweep_bigq<L, false>), grid, dim3(kPcThreads), pl.lds_bytes, st, q);
@@ -1483,7 +1500,7 @@ static hipError_t launch_L(const SweepParams &p0, const SizePlan &pl, hipStream_
     return hipGetLastError();
 }
 
-#define MC_FOR_EACH_SIZE(X) X(4) X(8) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(64) X(128) X(256)
+#define MC_FOR_EACH_SIZE(X) X(4) X(8) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(64) X(100) X(128) X(256)
 
 hipError_t prepare_sweeps(const SizeDev &s, const SizePlan &p) {
     switch (s.L) {

@@ -157,7 +157,8 @@ def _smooth_weight(L, bs, seed):
 
 @pytest.mark.parametrize("L,bs,cpb,kind", [(128, 1, None, 8), (128, 1, 13, 8), (128, 1, 32, 8), (128, 1, 20, 8),
                                              (128, 1, 40, 5), (128, 1, 64, 6), (128, 0, 16, 9), (256, 1, None, 9),
-                                             (256, 1, 5, 9), (256, 1, 32, 9)])
+                                             (256, 1, 5, 9), (256, 1, 32, 9), (100, 1, None, 8), (100, 1, 32, 8),
+                                             (100, 0, 16, 9)])
 def test_large_lattice_kernels_bitexact(L, bs, cpb, kind):
     """The streamed-row kernels of the large lattices against the oracle over
     two rounds with a ragged last workgroup: four lanes per chain (the
@@ -166,7 +167,8 @@ def test_large_lattice_kernels_bitexact(L, bs, cpb, kind):
     fit (one level per bin at L = 128, L = 256), in global memory (kind 9);
     one lane per chain (more than 32 chains per workgroup) with the table in
     LDS (kind 5) or, where 64 chains leave no room for it, in global memory
-    (kind 6)."""
+    (kind 6).  L = 100 (the paper's lattice) has a partial last word per
+    row and runs the four-lane kinds only."""
     mc = _mc()
     P, M = 70, 2
     w = _smooth_weight(L, bs, 11)
