@@ -18,8 +18,8 @@ graph-captured iterations), l128 (L = 128, 8192 chains), thermo (the reduced
 reweighting of code (ii) at L = 256 for 4096 inverse temperatures), fig2 (the
 comparison of Fig. 2: detailed-balance joints against naive splices at L = 20,
 measured by code (ii) against the exact energy), fig1 (the comparison of
-Fig. 1 at L = 64 and 128: weights from the learned initialiser, E, C, F, S of
-code (ii) against the exact finite lattice), topup (Algorithm step 6 with
+Fig. 1 at L = 64 and the paper's L = 100: weights from the learned
+initialiser, E, C, F, S of code (ii) against the exact finite lattice), topup (Algorithm step 6 with
 joints in chain order, in energy order and naive, at L = 20), learned
 (iterations to flat at L = 64 from the network's proposal against ln w = 0),
 and copy (a plain device copy of known size, to calibrate the HBM byte
@@ -67,7 +67,7 @@ def parse():
     ap.add_argument("--cpu-sweeps", type=int, default=4000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
-    ap.add_argument("--out-npz", default=None, help="fig1: also save the L = 64 and L = 128 weights there")
+    ap.add_argument("--out-npz", default=None, help="fig1: also save the L = 64 and L = 100 weights there")
     return ap.parse_args()
 
 
@@ -442,13 +442,14 @@ def bench_topup(a, torch, mc):
 
 
 def bench_fig1(a, torch, mc):
-    """The comparison of Fig. 1 (Sec. 5) at L = 128, the compiled size nearest
-    the paper's L = 100: E/N, C, F/N and S/N from code (ii) against the exact
-    finite-lattice values (Kaufman's ln Z and its beta derivatives).  The
-    weight comes from the learned initialiser instead of 1300 iterations:
-    converged weights of L = 8, 16, 32 (recursions from ln w = 0) train the
-    network, its proposal for L = 64 is run to flat, the network is trained
-    again with L = 64 added, and its proposal for L = 128 is run to flat."""
+    """The comparison of Fig. 1 (Sec. 5) at the paper's L = 100 (and L = 64):
+    E/N, C, F/N and S/N from code (ii) against the exact finite-lattice values
+    (Kaufman's ln Z and its beta derivatives).  The weight comes from the
+    learned initialiser instead of 1300 iterations: converged weights of
+    L = 8, 16, 32 (recursions from ln w = 0) train the network, its proposal
+    for L = 64 is run to flat, the network is trained again with L = 64 added,
+    and its proposal for L = 100 is run to flat (at most --iters
+    iterations)."""
     from paper_0812_2964_amd.learned import Initializer, run_to_flat
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     import mpmath
@@ -457,7 +458,7 @@ def bench_fig1(a, torch, mc):
     P, M = a.chains or 4096, a.sweeps or 2000
     P_big = 8192
     cap = a.iters or 150
-    L = 128
+    L = 100
     N = L * L
     t0 = time.perf_counter()
     ini = Initializer(seed=1)
@@ -477,15 +478,15 @@ def bench_fig1(a, torch, mc):
         ini.add(64, w64)
         ini.fit(steps=4000, lr=2e-3)
     log("bench fig1: L = 64 flat at %s, retrained (%.1f s)" % (flat, time.perf_counter() - t0))
-    w128, flat, done = run_to_flat(L, P_big, M, cap, lnW0=ini.predict(L), extra=4,
-                                   progress=lambda d: log("bench fig1: L = 128, %d iterations" % d)
-                                   if d % 20 == 0 else None)
+    wL, flat, done = run_to_flat(L, P_big, M, cap, lnW0=ini.predict(L), extra=4,
+                                 progress=lambda d: log("bench fig1: L = %d, %d iterations" % (L, d))
+                                 if d % 20 == 0 else None)
     stages[L] = {"from": "network (8, 16, 32, 64)", "first_flat": flat, "iterations": done, "chains": P_big}
     att += done * P_big * M * N
     dt = time.perf_counter() - t0
     if a.out_npz:
-        np.savez(a.out_npz, lnW64=w64, lnW128=w128)
-    betas = np.round(np.concatenate([np.arange(0.1, 0.4, 0.05), np.arange(0.40, 0.48, 0.01),
+        np.savez(a.out_npz, lnW64=w64, lnW100=wL)
+    betas = np.round(np.concatenate([np.arange(0.1, 0.375, 0.05), np.arange(0.40, 0.475, 0.01),
                                      np.arange(0.5, 1.01, 0.1)]), 4)
 
     def compare(Ls, w):
@@ -523,7 +524,7 @@ def bench_fig1(a, torch, mc):
     res["stages"] = {str(k): v for k, v in stages.items()}
     res["betas"] = betas.tolist()
     res["L64"] = compare(64, w64)
-    res["L128"] = compare(L, w128)
+    res["L%d" % L] = compare(L, wL)
     return res
 
 
