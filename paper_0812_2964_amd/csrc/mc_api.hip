@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <algorithm>
+#include <array>
 #include <cstring>
 #include <set>
 #include <string>
@@ -373,16 +374,16 @@ static hipError_t trace_ends(mc_ctx *ctx, const SizeDev &d, const void *trace_de
 // CRC-32 of the IEEE 802.3 / zlib definition (reflected polynomial
 // 0xEDB88320, initial and final complement), table driven.
 static uint32_t crc32_of(const unsigned char *p, size_t n) {
-    static uint32_t table[256];
-    static bool ready = false;
-    if (!ready) {
+    // built once; the initialisation of a function-local static is thread-safe
+    static const std::array<uint32_t, 256> table = [] {
+        std::array<uint32_t, 256> t{};
         for (uint32_t i = 0; i < 256; ++i) {
             uint32_t c = i;
             for (int k = 0; k < 8; ++k) c = (c & 1u) ? 0xEDB88320u ^ (c >> 1) : c >> 1;
-            table[i] = c;
+            t[i] = c;
         }
-        ready = true;
-    }
+        return t;
+    }();
     uint32_t c = 0xFFFFFFFFu;
     for (size_t i = 0; i < n; ++i) c = table[(c ^ p[i]) & 0xFFu] ^ (c >> 8);
     return c ^ 0xFFFFFFFFu;
