@@ -1,0 +1,58 @@
+"""Host logic of the benchmark script (no GPU): the multi-core oracle leg of
+its CPU baseline splits the chains into contiguous blocks keyed by their global
+index, which is the same computation as one run over all of them; the
+`--gpus` guard; the traffic figure is only taken from a counter summary of the
+current kernel source and workload."""
+import os
+import subprocess
+import sys
+import threading
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+sys.path.insert(0, ROOT)
+
+import oracle as O  # noqa: E402
+
+
+def test_threaded_blocks_equal_one_run():
+    import bench
+
+    L, blk, T, M = 8, 3, 4, 25
+    w = np.random.default_rng(3).normal(0, 2.0, O.n_bins(L, 1))
+    whole = O.Run(L, T * blk, seed=1, bin_shift=1, lnW=w)
+    tr, h = whole.run(M)
+    runs = [O.Run(L, blk, seed=1, bin_shift=1, lnW=w, chain_offset=t * blk) for t in range(T)]
+    out = [None] * T
+
+    def go(t):
+        out[t] = runs[t].run(M)
+
+    ths = [threading.Thread(target=go, args=(t,)) for t in range(T)]
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
+    assert np.array_equal(np.concatenate([o[0] for o in out]), tr)
+    assert np.array_equal(sum(o[1] for o in out), h)
+    assert np.array_equal(np.concatenate([r.spins for r in runs]), whole.spins)
+    assert 1 <= bench.cpu_threads() <= 16
+    cb = bench.cpu_baseline(L, w, 4, 20)
+    assert cb["kind"] == "oracle" and cb["cores"] == bench.cpu_threads() and cb["value"] > 0
+
+
+def test_more_than_one_gpu_is_refused():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert p.returncode != 0 and "one GPU" in (p.stdout + p.stderr)
+
+
+def test_traffic_only_for_current_source_and_workload():
+    import bench
+
+    t = bench.traffic_from_profiles(32, 4096, 100000)
+    assert t is None or t > 8e8
+    assert bench.traffic_from_profiles(32, 4096, 99999) is None
+    assert bench.traffic_from_profiles(16, 4096, 100000) is None
