@@ -208,9 +208,13 @@ mc_status mc_set_seam(mc_ctx *ctx, int32_t size_idx, int32_t seam);
    hold *len >= that size, and *len receives it.  MC_EINVAL for a null len or
    a short buffer.
    mc_set_state: the context must have been created with the same sizes,
-   chain counts, seeds and bins (MC_EINVAL otherwise); a blob that fails its
-   magic, version, length or checksum, or holds a non-finite ln w, gives
-   MC_ECORRUPT and changes nothing.  Graphs of the context stay valid. */
+   chain counts, seeds and bins (MC_EINVAL otherwise).  A blob that fails its
+   magic, version, length or checksum, holds a non-finite ln w, counters out of
+   range (a seam outside -1..N, pending configurations or sweeps outside
+   0..2^31-1), lattice bits set beyond L in a row's last word, or a chain whose
+   level is not half its broken bonds gives MC_ECORRUPT and changes nothing:
+   the kernels index their tables by level, so the state is checked on the
+   host before it is copied.  Graphs of the context stay valid. */
 mc_status mc_get_state(mc_ctx *ctx, void *buf, size_t *len);
 mc_status mc_set_state(mc_ctx *ctx, const void *buf, size_t len);
 

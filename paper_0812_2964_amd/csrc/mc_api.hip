@@ -401,6 +401,55 @@ static size_t state_size_of(const SizeDev &d) {
            (size_t)d.n_bins * 8;
 }
 
+// Check the chain state of one size in a blob before it reaches the kernels,
+// which index the threshold tables and histograms by level: every site bit
+// beyond L in a row's last word is zero (as the kernels keep it), and each
+// chain's level is half its number of broken bonds (Sec. 4.1, J = 1: level
+// (E + 2N)/4).  lat: [L*W][P] words, chain-interleaved; lev: [P].  Returns the
+// first chain that fails, or -1.
+static int64_t bad_chain(const SizeDev &d, const unsigned char *lat, const unsigned char *lev, int32_t *why) {
+    const int L = d.L, W = d.W, P = d.P;
+    const int nb = L - 32 * (W - 1);  // site bits in a row's last word
+    const uint32_t last_mask = nb == 32 ? 0xFFFFFFFFu : (1u << nb) - 1u;
+    auto word = [&](int row, int w, int c) {
+        uint32_t v;
+        std::memcpy(&v, lat + ((size_t)(row * W + w) * P + c) * 4, 4);
+        return v;
+    };
+    std::vector<uint32_t> cur((size_t)W), first((size_t)W);
+    for (int c = 0; c < P; ++c) {
+        int64_t broken = 0;
+        for (int w = 0; w < W; ++w) first[w] = word(0, w, c);
+        for (int y = 0; y < L; ++y) {
+            for (int w = 0; w < W; ++w) cur[w] = word(y, w, c);
+            if (cur[W - 1] & ~last_mask) {
+                *why = 1;
+                return c;
+            }
+            for (int w = 0; w < W; ++w) {
+                // right neighbours of the word's sites: the next site bit,
+                // wrapping from site L-1 to site 0
+                uint32_t right, mask = 0xFFFFFFFFu;
+                if (w < W - 1) {
+                    right = (cur[w] >> 1) | (cur[w + 1] << 31);
+                } else {
+                    right = (cur[w] >> 1) | ((cur[0] & 1u) << (nb - 1));
+                    mask = last_mask;
+                }
+                const uint32_t down = y + 1 < L ? word(y + 1, w, c) : first[w];
+                broken += __builtin_popcount((cur[w] ^ right) & mask) + __builtin_popcount((cur[w] ^ down) & mask);
+            }
+        }
+        int32_t m;
+        std::memcpy(&m, lev + (size_t)c * 4, 4);
+        if ((int64_t)m * 2 != broken) {
+            *why = 2;
+            return c;
+        }
+    }
+    return -1;
+}
+
 void mcgpu::set_last_error(const char *msg) { g_err = msg; }
 
 extern "C" {
@@ -835,6 +884,20 @@ mc_status mc_set_state(mc_ctx *ctx, const void *buf, size_t len) {
             get32(at + 24) != d.c_off)
             return fail(MC_EINVAL, "the state's sizes differ from the context's");
         if (at + state_size_of(d) > len) return fail(MC_ECORRUPT, "state too short");
+        const int64_t pending = (int64_t)get64(at + 28), last_M = (int64_t)get64(at + 36);
+        const int32_t sigma = (int32_t)get32(at + 52), flat = (int32_t)get32(at + 56);
+        const int64_t retained = (int64_t)get64(at + 60), retained_last = (int64_t)get64(at + 68);
+        const int32_t iter = (int32_t)get32(at + 76), flat_iter = (int32_t)get32(at + 80);
+        if (pending < 0 || pending > 0x7FFFFFFFll || last_M < 0 || last_M > 0x7FFFFFFFll || sigma < -1 ||
+            sigma > d.N || (flat != 0 && flat != 1) || retained < 0 || retained_last < 0 || iter < 0 ||
+            flat_iter < 0 || flat_iter > iter)
+            return fail(MC_ECORRUPT, "the state's counters are out of range");
+        const size_t lat_at = at + 84, lev_at = lat_at + (size_t)d.L * d.W * d.P * 4;
+        int32_t why = 0;
+        const int64_t c = bad_chain(d, b + lat_at, b + lev_at, &why);
+        if (c >= 0)
+            return fail(MC_ECORRUPT, why == 1 ? "chain %lld: lattice bits set beyond L" :
+                                                "chain %lld: level does not match its lattice", (long long)c);
         const size_t lnw = at + state_size_of(d) - (size_t)d.n_bins * 8;
         for (int k = 0; k < d.n_bins; ++k) {
             double v;

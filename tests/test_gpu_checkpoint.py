@@ -132,3 +132,77 @@ def test_blob_checksum_and_refusals():
         assert "MC_EINVAL" in str(e.value)
         B.close()
     A.close()
+
+
+def _reseal(blob):
+    """The blob with its CRC-32 recomputed (the field at bytes 8..11 zeroed)."""
+    b = bytearray(blob)
+    b[8:12] = b"\0\0\0\0"
+    b[8:12] = zlib.crc32(bytes(b)).to_bytes(4, "little")
+    return bytes(b)
+
+
+def test_state_checked_before_the_kernels_see_it():
+    """Blobs with a valid checksum but a state the kernels could not run from
+    are refused (MC_ECORRUPT, context unchanged): a level that is not half the
+    chain's broken bonds, a lattice bit beyond L, a seam outside -1..N, a
+    negative pending count.  A consistent edit (one spin flipped, its level
+    moved with it) is taken, and the chain then runs as the oracle does from
+    that state."""
+    import oracle as O
+
+    mc = _mc()
+    L, P, bs, seed, M = 20, 16, 1, 4, 30
+    N, W = L * L, 1
+    A = mc.Context([(L, P, seed, bs)])
+    _iterate(A, M, 2)
+    blob = A.get_state()
+    size_at = 24
+    lat_at = size_at + 84
+    lev_at = lat_at + L * W * P * 4
+
+    def edit(fn):
+        b = bytearray(blob)
+        fn(b)
+        return _reseal(bytes(b))
+
+    def put32(b, pos, v):
+        b[pos:pos + 4] = int(v & 0xFFFFFFFF).to_bytes(4, "little")
+
+    def get32(b, pos, signed=False):
+        return int.from_bytes(bytes(b[pos:pos + 4]), "little", signed=signed)
+
+    bad = [
+        edit(lambda b: put32(b, lev_at + 3 * 4, get32(b, lev_at + 3 * 4) + 1)),
+        edit(lambda b: put32(b, lat_at + (7 * W * P + 2) * 4, get32(b, lat_at + (7 * W * P + 2) * 4) | (1 << 25))),
+        edit(lambda b: put32(b, size_at + 52, N + 1)),
+        edit(lambda b: b.__setitem__(slice(size_at + 28, size_at + 36), (-1).to_bytes(8, "little", signed=True))),
+    ]
+    before = A.get_state()
+    for k, damaged in enumerate(bad):
+        with pytest.raises(mc.MCError) as e:
+            A.set_state(damaged)
+        assert "MC_ECORRUPT" in str(e.value), k
+    assert A.get_state() == before
+
+    # a consistent edit: flip site (y, x) = (5, 7) of chain 9
+    c, y, x = 9, 5, 7
+    s = A.spins(c).copy()
+    s[y * L + x] = -s[y * L + x]
+    m = (O.energy(L, s) + 2 * N) // 4
+
+    def flip(b):
+        pos = lat_at + ((y * W + x // 32) * P + c) * 4
+        put32(b, pos, get32(b, pos) ^ (1 << (x % 32)))
+        put32(b, lev_at + c * 4, m)
+
+    A.set_state(edit(flip))
+    assert np.array_equal(A.spins(c), s) and A.levels()[c] == m
+    _, _, g = A.counters()
+    w = A.weights()
+    tr, h = A.new_trace(M), A.new_hist()
+    A.run_chains(M, tr, h)
+    s2, m2, otr, _ = O.sweeps(L, seed, bs, c, s, m, g, M, w)
+    assert np.array_equal(tr.cpu().numpy()[c].astype(np.int32), otr)
+    assert np.array_equal(A.spins(c), s2) and A.levels()[c] == m2
+    A.close()
