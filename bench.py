@@ -14,7 +14,8 @@ bounded sample of the same workload.
 
 Other workloads (--workload): recursion8 (L = 8, 16 chains, 10^4 sweeps, ten
 iterations from ln w = 0), batched (L = 16, 24, 32, 48, 64, 2048 chains each,
-graph-captured iterations), l128 (L = 128, 8192 chains), thermo (the reduced
+graph-captured iterations), l128 (L = 128, 8192 chains; --lattice 100 or 256
+for the paper's size or the largest), thermo (the reduced
 reweighting of code (ii) at L = 256 for 4096 inverse temperatures), fig2 (the
 comparison of Fig. 2: detailed-balance joints against naive splices at L = 20,
 measured by code (ii) against the exact energy), fig1 (the comparison of
@@ -63,6 +64,7 @@ def parse():
     ap.add_argument("--chains", type=int, default=None)
     ap.add_argument("--sweeps", type=int, default=None)
     ap.add_argument("--iters", type=int, default=None)
+    ap.add_argument("--lattice", type=int, default=128, help="l128: the lattice size (100, 128 or 256)")
     ap.add_argument("--cpu-chains", type=int, default=64)
     ap.add_argument("--cpu-sweeps", type=int, default=4000)
     ap.add_argument("--no-cpu", action="store_true")
@@ -272,7 +274,7 @@ def bench_batched(a, torch, mc):
 
 
 def bench_l128(a, torch, mc):
-    L, P = 128, a.chains or 8192
+    L, P = a.lattice, a.chains or 8192
     M = a.sweeps or 1000
     ctx = mc.Context([(L, P, 1, 1)])
     trace, hist, cut = ctx.new_trace(M), ctx.new_hist(), ctx.new_cut()
@@ -288,13 +290,13 @@ def bench_l128(a, torch, mc):
         torch.cuda.synchronize()
         if s >= a.warmup:
             times.append(e0.elapsed_time(e1) / 1e3)
-        log("bench l128: step %d done" % (s + 1))
+        log("bench l128 (L=%d): step %d done" % (L, s + 1))
     att = P * M * L * L
     sweep_s = sum(times) / len(times)
     cpb, kind, _ = ctx.launch()
     ctx.close()
     res = base_record(a, att / sweep_s, sweep_s * 1e3,
-                      {"workload": "2D Ising L=128, %d chains x %d sweeps per step, ln w = 0 start" % (P, M),
+                      {"workload": "2D Ising L=%d, %d chains x %d sweeps per step, ln w = 0 start" % (L, P, M),
                        "L": L, "chains": P, "sweeps_per_step": M, "kernel_kind": kind})
     res["roofline"] = roofline(att, sweep_s, None)
     res["roofline"]["kernel"] = kernel_name(kind, L) + " (mc_run_chains)"
