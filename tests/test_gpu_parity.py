@@ -299,27 +299,31 @@ def test_bench_workload_full_size_sampled():
     assert checked > 40
 
 
-def test_l128_workload_full_chain_count_sampled():
-    """L = 128 with the workload's 8192 chains in the default launch (the
-    quad streamed-row kernel, 32 chains on two consumer waves per workgroup,
-    the per-bin table in LDS), a non-trivial weight
-    (at ln w = 0 every flip is accepted), four sweeps: sampled chains replayed
-    by the oracle bit for bit; histograms and cut points through properties
-    that hold at any size."""
+@pytest.mark.parametrize("L,P,M,launch", [(128, 8192, 4, (32, 8)), (100, 8192, 4, (32, 8)), (256, 4096, 2, (16, 9))])
+def test_large_workload_full_chain_count_sampled(L, P, M, launch):
+    """The large-lattice workloads at their full chain counts in the default
+    launch: L = 128 and the paper's L = 100 with 8192 chains (the quad
+    streamed-row kernel, 32 chains on two consumer waves per workgroup, the
+    per-bin table in LDS), L = 256 with 4096 chains (16 chains per workgroup,
+    the per-bin table in global memory); a non-trivial weight (at ln w = 0
+    every flip is accepted): sampled chains replayed by the oracle bit for
+    bit; histograms and cut points through properties that hold at any
+    size."""
     mc = _mc()
-    L, P, M, N, bs = 128, 8192, 4, 128 * 128, 1
+    N, bs = L * L, 1
     nb = (N >> bs) + 1
     w = _smooth_weight(L, bs, 21)
     ctx = mc.Context([(L, P, 1, bs)])
     ctx.init_weights(w)
-    assert ctx.launch()[:2] == (32, 8)
+    assert ctx.launch()[:2] == launch
     tr, h, cut = ctx.new_trace(M), ctx.new_hist(), ctx.new_cut()
     ctx.run_chains(M, tr, h)
     raw = _np(h).copy()
     ctx.join(tr, cut, h)
     joined = _np(h).copy()
     levels = ctx.levels()
-    sampled = (0, 15, 16, 31, 32, 4095, 8191)  # 16: first chain of a workgroup's second consumer wave
+    # 16: first chain of a workgroup's second consumer wave (32 per workgroup)
+    sampled = (0, 15, 16, 31, 32, P // 2 - 1, P - 1)
     spins = {c: ctx.spins(c) for c in sampled}
     trace = _np(tr)
     cuts = _np(cut)
@@ -350,7 +354,8 @@ def test_l128_workload_full_chain_count_sampled():
 
 def test_batched_workload_full_chain_count_sampled():
     """The batched workload's sizes and chain counts (L = 16, 24, 32, 48, 64,
-    2048 chains each) in one persistent launch, with non-trivial weights:
+    2048 chains each) in one persistent launch in the autotuned plans the
+    benchmark times, with non-trivial weights:
     sampled chains of every size replayed by the oracle, raw histograms equal
     to the bincount of the traces."""
     mc = _mc()
@@ -359,6 +364,7 @@ def test_batched_workload_full_chain_count_sampled():
     ctx = mc.Context([(L, P, 1, bs) for L in Ls])
     for i, w in enumerate(ws):
         ctx.init_weights(w, i)
+    ctx.autotune(200)  # as the benchmark does; its probes leave the chains untouched
     assert all(ctx.launch(i)[2] for i in range(len(Ls)))  # batched
     trs = [ctx.new_trace(M, i) for i in range(len(Ls))]
     hs = [ctx.new_hist(i) for i in range(len(Ls))]
