@@ -373,6 +373,42 @@ __device__ void build_pair_table(uint4 *tbl, int tid, int nthreads) {
     }
 }
 
+// The same table for the quad-speculative consumer, with bytes 1 and 2 of .y
+// and .z swapped:
+//   .y / .z = { threshold of x, level move if only x accepted, threshold of
+//               x+1 if x accepted, level move if both accepted },
+// so that all three level moves sit at odd bytes (1 and 3 of .y / .z, 3 of
+// .x) and a lane picks the move of its assumed outcome, sign-extended, with
+// one byte permute (v_perm_b32 sign codes exist for bytes 1, 3, 5, 7 only).
+__device__ void build_pair_table_q(uint4 *tbl, int tid, int nthreads) {
+    auto pack = [](int b0, int b1, int b2, int b3) {
+        return (uint32_t)(b0 & 255) | ((uint32_t)(b1 & 255) << 8) | ((uint32_t)(b2 & 255) << 16) |
+               ((uint32_t)(b3 & 255) << 24);
+    };
+    for (int i = tid; i < 64; i += nthreads) {
+        const int qx = (i & 1) + 2 * ((i >> 2) & 1);
+        const int qx1 = ((i >> 1) & 1) + 2 * ((i >> 3) & 1);
+        const int hx = (i >> 4) & 1, hx1 = (i >> 5) & 1;
+        const int an0 = qx1 + hx1, an1 = qx1 + (hx1 ^ 1);
+        uint32_t v[2];
+        for (int a = 0; a < 2; ++a) {
+            const int ax = qx + (hx ^ a);
+            const int dx = kLevelBytes * (2 - ax);
+            v[a] = pack(-4 * ax, dx, dx - 4 * an1, dx + kLevelBytes * (2 - an1));
+        }
+        tbl[i] = make_uint4(pack(-4 * an0, 0, 0, kLevelBytes * (2 - an0)), v[0], v[1], 0u);
+    }
+}
+
+// v_perm_b32 selectors over {.x (bytes 4-7), V = .y or .z (bytes 0-3)} of a
+// build_pair_table_q entry giving, sign-extended, the level move of pair
+// outcome j = (x accepted) + 2 (x+1 accepted): 0; byte 1 of V; byte 3 of .x
+// (byte 7); byte 3 of V.  Codes 8, 9, 11 repeat the sign bit of bytes 1, 3, 7;
+// code 12 gives a zero byte.
+__device__ __forceinline__ uint32_t quad_move_selector(uint32_t j) {
+    return j == 0 ? 0x0C0C0C0Cu : j == 1 ? 0x08080801u : j == 2 ? 0x0B0B0B07u : 0x09090903u;
+}
+
 // One row of the consumer, two sites at a time.  mib is the LDS byte address of
 // entry a = 4 of the current level of the threshold table, so the threshold of
 // a flip with `anti` anti-aligned neighbours is at mib - 4 anti and an accepted
@@ -602,14 +638,16 @@ __device__ __forceinline__ uint32_t quad_bcast(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
 }
 
-// One row of the quad consumer.  hxm, hym: all ones in lanes that assume site
-// x (x+1) of pair p accepted; jq: the lane's place in its quad; hf0 / hf1: its
-// result flags (jq, its assumed outcome of pair p, in bits 28-29, plus bit 30
-// when pair p+1's first site is accepted), so that the word selected for the
-// quad carries the step's four flips in bits 28-31.
+// One row of the quad consumer (pair table of build_pair_table_q).  selh: the
+// byte-permute selector of the level move of the lane's assumed outcome of
+// pair p (quad_move_selector); hym: all ones in lanes that assume site x+1 of
+// pair p accepted; jq: the lane's place in its quad; hf0 / hf1: its result
+// flags (jq, its assumed outcome of pair p, in bits 28-29, plus bit 30 when
+// pair p+1's first site is accepted), so that the word selected for the quad
+// carries the step's four flips in bits 28-31.
 template <int L>
 __device__ __forceinline__ void pcq_row(Row<L> &cur, const Row<L> &up, const Row<L> &dn, uint32_t &mib,
-                                        uint32_t pair_addr, const uint4 *urow, int cpb, uint32_t hxm, uint32_t hym,
+                                        uint32_t pair_addr, const uint4 *urow, int cpb, uint32_t selh, uint32_t hym,
                                         uint32_t jq, uint32_t hf0, uint32_t hf1) {
     static_assert(L >= 8 && L % 4 == 0, "two pairs per step, site 0 decided before the last step");
     constexpr int W = (L + 31) / 32;
@@ -673,21 +711,19 @@ __device__ __forceinline__ void pcq_row(Row<L> &cur, const Row<L> &up, const Row
         const uint32_t V = aprev ? ea.z : ea.y;
         // pair p+1 from the state left by the assumed outcome of pair p: the
         // level move is byte 3 of V (both accepted), byte 3 of ea.x (only x+1),
-        // byte 2 of V (only x) or 0; selected with lane masks, without branches
-        const uint32_t ew = (V & hxm) | (ea.x & ~hxm);
-        const int32_t Eh = ((int32_t)(ew << (8u & ~hym)) >> 24) & (int32_t)(hxm | hym);
-        const uint32_t mh = mib + (uint32_t)Eh;
+        // byte 1 of V (only x) or 0, picked by the lane's selector
+        const uint32_t mh = mib + __builtin_amdgcn_perm(ea.x, V, selh);
         const uint32_t Vq = (eb.z & hym) | (eb.y & ~hym);
         const uint32_t tx = lds_load(mib + sbyte(V, 0));
         const uint32_t t0 = lds_load(mib + sbyte(ea.x, 0));
-        const uint32_t t1 = lds_load(mib + sbyte(V, 1));
+        const uint32_t t1 = lds_load(mib + sbyte(V, 2));
         const uint32_t qx = lds_load(mh + sbyte(Vq, 0));
         const uint32_t q0 = lds_load(mh + sbyte(eb.x, 0));
-        const uint32_t q1 = lds_load(mh + sbyte(Vq, 1));
+        const uint32_t q1 = lds_load(mh + sbyte(Vq, 2));
         const bool bx = u4.z <= qx;
         const uint32_t qn = bx ? q1 : q0;
         const uint32_t nA = mh + (uint32_t)(bx ? sbyte(Vq, 3) : sbyte(eb.x, 3));
-        const uint32_t nB = mh + (uint32_t)(bx ? sbyte(Vq, 2) : 0);
+        const uint32_t nB = mh + (uint32_t)(bx ? sbyte(Vq, 1) : 0);
         const bool bx1 = u4.w <= qn;
         // result of the assumption: next state, the assumed outcome of pair p
         // in bits 28-29 and the two decisions of pair p+1 in bits 30, 31
@@ -729,7 +765,7 @@ __device__ __forceinline__ void sweep_tile_pcq(const SizeDev &s, int c0, int cpb
     const bool consumer = wave == 0;
     const bool active = consumer && cl < cpb && c < s.P;
     const bool lead = active && j == 0;  // one lane per chain for the global writes and atomics
-    const uint32_t hxm = 0u - (uint32_t)(j & 1), hym = 0u - (uint32_t)((j >> 1) & 1);
+    const uint32_t selh = quad_move_selector((uint32_t)j), hym = 0u - (uint32_t)((j >> 1) & 1);
     const uint32_t hf0 = (uint32_t)j << 28, hf1 = hf0 | (1u << 30);
     const uint32_t k0 = s.seed, k1 = (uint32_t)L;
     const uint32_t g0 = s.ctl->g;
@@ -738,7 +774,7 @@ __device__ __forceinline__ void sweep_tile_pcq(const SizeDev &s, int c0, int cpb
         stab[i] = s.tab[(size_t)m * 8 + (i - 5 * m)];
     }
     for (int i = threadIdx.x; i < s.n_bins; i += blockDim.x) shist[i] = 0;
-    build_pair_table(ptbl, threadIdx.x, blockDim.x);
+    build_pair_table_q(ptbl, threadIdx.x, blockDim.x);
     if (lead)
         for (int w = 0; w < L * W; ++w) slat[w * cpb + cl] = s.lat[(size_t)w * s.P + c];
     const int np = blockDim.x - 64, pt = threadIdx.x - 64;
@@ -770,7 +806,7 @@ __device__ __forceinline__ void sweep_tile_pcq(const SizeDev &s, int c0, int cpb
             }
             for (int r = 0; r < R; ++r) {
                 const int y = y0 + r;
-                pcq_row<L>(cur, up, dn, mib, pair_addr, ub + (size_t)r * (L / 4) * cpb + cl, cpb, hxm, hym,
+                pcq_row<L>(cur, up, dn, mib, pair_addr, ub + (size_t)r * (L / 4) * cpb + cl, cpb, selh, hym,
                            (uint32_t)j, hf0, hf1);
                 // the four lanes of the quad hold the same row
 #pragma unroll
