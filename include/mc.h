@@ -271,6 +271,11 @@ mc_status mc_get_progress(mc_ctx *ctx, int32_t size_idx, int32_t *updates, int32
    are more chains than 16 per compute unit.  mc_set_chains_per_block picks
    kind 7 (L <= 64) or 8 / 9 (L >= 100) where the chains per workgroup allow
    it (at most 16, resp. 32), else kind 4 or 5 / 6.
+   mc_set_launch: the kernel kind (0..9) and chains per workgroup of one
+   size, for a kind other than the one mc_set_chains_per_block would pick
+   (kind 4 or a one-wave kind at 16 chains, say); MC_EINVAL when that kind
+   cannot run the size at that many chains per workgroup (the configuration
+   is then unchanged).
    mc_autotune: times probe_sweeps sweeps of every size on copies of the chain
    state for 16, 32 and 64 chains per workgroup, with the producer/consumer
    kinds and with the one-wave kinds, and keeps the fastest; when the sizes
@@ -278,9 +283,10 @@ mc_status mc_get_progress(mc_ctx *ctx, int32_t size_idx, int32_t *updates, int32
    chains per workgroup everywhere and (up to six sizes) every mix of each
    size's fastest plan and its widest one, and keeps the fastest
    (chains_per_block_out: n_sizes values, nullable).  The chains are not
-   advanced.  Both setters fail with MC_ESTATE while graphs of the context
+   advanced.  The setters fail with MC_ESTATE while graphs of the context
    exist. */
 mc_status mc_set_chains_per_block(mc_ctx *ctx, int32_t size_idx, int32_t chains_per_block);
+mc_status mc_set_launch(mc_ctx *ctx, int32_t size_idx, int32_t kind, int32_t chains_per_block);
 mc_status mc_get_launch(mc_ctx *ctx, int32_t size_idx, int32_t *chains_per_block, int32_t *kind, int32_t *batched);
 mc_status mc_autotune(mc_ctx *ctx, int64_t probe_sweeps, int32_t *chains_per_block_out);
 

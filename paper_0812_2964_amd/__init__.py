@@ -22,7 +22,7 @@ _STATUS = {0: "MC_OK", -1: "MC_EINVAL", -2: "MC_ENOMEM", -3: "MC_ENODEV", -4: "M
 # Symbols declared in include/mc.h (checked by the CPU test-suite).
 EXPORTED = ["mc_create", "mc_destroy", "mc_n_bins", "mc_trace_elem_bytes", "mc_lattice_words", "mc_init_weights",
             "mc_run_chains", "mc_join", "mc_update_weights", "mc_get_levels", "mc_get_lattice", "mc_get_counters",
-            "mc_get_weights", "mc_get_progress", "mc_set_chains_per_block", "mc_get_launch", "mc_autotune",
+            "mc_get_weights", "mc_get_progress", "mc_set_chains_per_block", "mc_set_launch", "mc_get_launch", "mc_autotune",
             "mc_graph_create", "mc_graph_launch", "mc_graph_destroy", "mc_sync", "mc_last_error",
             "mc_mlp_n_params", "mc_mlp_workspace_bytes", "mc_mlp_init", "mc_mlp_forward", "mc_mlp_loss_grad",
             "mc_mlp_train", "mc_mlp_targets", "mc_mlp_predict_weights", "mc_thermo", "mc_iterate_topup",
@@ -73,6 +73,7 @@ def lib():
     L.mc_get_weights.argtypes = [p, i32, p, i32]
     L.mc_get_progress.argtypes = [p, i32, p, p, p, p]
     L.mc_set_chains_per_block.argtypes = [p, i32, i32]
+    L.mc_set_launch.argtypes = [p, i32, i32, i32]
     L.mc_get_launch.argtypes = [p, i32, p, p, p]
     L.mc_autotune.argtypes = [p, i64, p]
     L.mc_graph_create.argtypes = [p, i64, i32, p, p, p, i32, ctypes.POINTER(p)]
@@ -309,6 +310,10 @@ class Context:
     # -- launch configuration (speed only, never results) ------------------
     def set_chains_per_block(self, cpb, i=0):
         _check(lib().mc_set_chains_per_block(self._h, i, int(cpb)))
+
+    def set_launch(self, kind, cpb, i=0):
+        """Kernel kind and chains per workgroup of size i (mc_set_launch)."""
+        _check(lib().mc_set_launch(self._h, i, int(kind), int(cpb)))
 
     def launch(self, i=0):
         """(chains per block, kernel kind, batched flag)"""

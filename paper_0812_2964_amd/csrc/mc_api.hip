@@ -990,6 +990,22 @@ mc_status mc_set_chains_per_block(mc_ctx *ctx, int32_t i, int32_t chains_per_blo
     return MC_OK;
 }
 
+mc_status mc_set_launch(mc_ctx *ctx, int32_t i, int32_t kind, int32_t chains_per_block) {
+    mc_status st = check_size(ctx, i);
+    if (st != MC_OK) return st;
+    if (chains_per_block < 1 || chains_per_block > 64) return fail(MC_EINVAL, "chains_per_block must be 1..64");
+    if (kind < 0 || kind > kSweepBigQGlb) return fail(MC_EINVAL, "kind must be 0..%d", (int)kSweepBigQGlb);
+    if (ctx->live_graphs > 0) return fail(MC_ESTATE, "the launch configuration is fixed while graphs exist");
+    const SizePlan p = plan_kind(ctx->sizes[i].dev, kind, chains_per_block);
+    if (p.kind != kind || p.cpb != chains_per_block)
+        return fail(MC_EINVAL, "size %d: kind %d does not run L=%d at %d chains per workgroup", i, kind,
+                    ctx->sizes[i].dev.L, chains_per_block);
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->sizes[i].plan = p;
+    HIP_OR_FAIL(ctx, rebuild_launch(ctx));
+    return MC_OK;
+}
+
 mc_status mc_get_launch(mc_ctx *ctx, int32_t i, int32_t *chains_per_block, int32_t *kind, int32_t *batched) {
     mc_status st = check_size(ctx, i);
     if (st != MC_OK) return st;

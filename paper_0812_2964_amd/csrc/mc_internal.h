@@ -70,6 +70,9 @@ struct Tile {
 // Kernel launchers (mc_kernels.hip).  All enqueue on `st` and return the
 // launch status.
 SizePlan plan_sweeps(const SizeDev &s, int chains_per_block, bool allow_pc = true);
+// The plan a kernel kind would get at chains_per_block (its kind differs from
+// `kind` when that kind cannot run the size at that many chains per block).
+SizePlan plan_kind(const SizeDev &s, int kind, int chains_per_block);
 bool batchable(const SizePlan &p);
 hipError_t prepare_sweeps(const SizeDev &s, const SizePlan &p);  // kernel attributes; call outside capture
 hipError_t prepare_batched(size_t lds_bytes);

@@ -1450,6 +1450,53 @@ SizePlan plan_sweeps(const SizeDev &s, int cpb, bool allow_pc) {
     return p;
 }
 
+SizePlan plan_kind(const SizeDev &s, int kind, int cpb) {
+    // the one-wave kinds come from the plan without producer waves
+    SizePlan p = plan_sweeps(s, cpb, kind != kSweepLdsTab && kind != kSweepLds && kind != kSweepGlobal);
+    if (p.kind == kind || !compiled_size(s.L)) return p;
+    // kinds the default plan passes over for a faster one at this size and cpb
+    SizePlan q = p;
+    auto first_fit = [&](int k, auto layout_total) {
+        for (int R = 8; R >= 1; R /= 2) {
+            if (s.L % R) continue;
+            const size_t total = layout_total(R);
+            if (total <= kLdsMax) {
+                q.kind = k;
+                q.R = R;
+                q.lds_bytes = total;
+                return true;
+            }
+        }
+        return false;
+    };
+    if (kind == kSweepPC && s.L <= 64 && s.L % 4 == 0) {
+        if (first_fit(kind, [&](int R) { return pc_layout(s.L, s.W, s.N, s.n_bins, p.cpb, R).total; })) return q;
+    } else if ((kind == kSweepBig || kind == kSweepBigGlb) && big_size(s.L)) {
+        const bool tl = kind == kSweepBig;
+        if (first_fit(kind, [&](int R) { return R <= 4 ? big_layout(s.L, s.n_bins, s.tab_r, p.cpb, R, tl).total
+                                                        : kLdsMax + 1; }))
+            return q;
+    } else if (kind == kSweepBigQGlb && bigq_size(s.L) && p.cpb <= kBigqMaxChains) {
+        if (first_fit(kind, [&](int R) { return R <= 4 ? big_layout(s.L, s.n_bins, s.tab_r, p.cpb, R, false).total
+                                                        : kLdsMax + 1; }))
+            return q;
+    } else if (kind == kSweepLds && s.L <= 64) {
+        const size_t total = (size_t)s.L * s.W * p.cpb * 4 + (size_t)s.n_bins * 4;
+        if (total <= kLdsMax) {
+            q.kind = kSweepLds;
+            q.R = 0;
+            q.lds_bytes = total;
+            return q;
+        }
+    } else if (kind == kSweepGlobal && s.L <= 64) {
+        q.kind = kSweepGlobal;
+        q.R = 0;
+        q.lds_bytes = 0;
+        return q;
+    }
+    return p;
+}
+
 bool batchable(const SizePlan &p) {
     return p.kind == kSweepLdsTab || p.kind == kSweepLds || p.kind == kSweepPC || p.kind == kSweepPCQ;
 }

@@ -408,3 +408,35 @@ def test_producer_consumer_kernels_bitexact(L, P, bs, M, cpb, kind):
         assert_round_equal(g, o)
     assert_state_equal(ctx, R)
     ctx.close()
+
+
+def test_set_launch_kinds_and_refusals():
+    """mc_set_launch picks a kind other than the default at the same chains
+    per workgroup (the pair kernel and a one-wave kernel at 16 chains, where
+    mc_set_chains_per_block takes the quad kernel), with the same results as
+    the oracle; a kind that cannot run the size there, a kind out of range or
+    a chains-per-workgroup count out of range is refused and changes
+    nothing."""
+    mc = _mc()
+    L, P, bs, M = 16, 40, 1, 8
+    w = _smooth_weight(L, bs, 77)
+    for kind in (4, 0):
+        ctx = mc.Context([(L, P, 2, bs)])
+        ctx.init_weights(w)
+        ctx.set_launch(kind, 16)
+        assert ctx.launch()[:2] == (16, kind)
+        R = O.Run(L, P, seed=2, bin_shift=bs, lnW=w)
+        g = gpu_round(ctx, M)
+        o = oracle_round(R, M)
+        assert_round_equal(g, o)
+        ctx.close()
+    ctx = mc.Context([(32, 20, 1, 1), (128, 20, 1, 1)])
+    before = ctx.launch(0), ctx.launch(1)
+    for i, kind, cpb in ((0, 7, 17), (0, 8, 16), (1, 7, 16), (0, 10, 16), (0, 7, 0), (1, 8, 33)):
+        with pytest.raises(mc.MCError) as e:
+            ctx.set_launch(kind, cpb, i)
+        assert e.value.status == mc.MC_EINVAL, (i, kind, cpb)
+    assert (ctx.launch(0), ctx.launch(1)) == before
+    ctx.set_launch(7, 8, 0)
+    assert ctx.launch(0)[:2] == (8, 7)
+    ctx.close()
