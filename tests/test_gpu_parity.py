@@ -440,3 +440,30 @@ def test_set_launch_kinds_and_refusals():
     ctx.set_launch(7, 8, 0)
     assert ctx.launch(0)[:2] == (8, 7)
     ctx.close()
+
+
+@pytest.mark.parametrize("L,P,kinds", [(16, 45, (0, 1, 2, 4, 7)), (64, 19, (0, 1, 2, 4, 7)),
+                                       (128, 40, (5, 6, 8, 9)), (100, 21, (8, 9))])
+def test_every_kernel_kind_bitexact(L, P, kinds):
+    """Every kernel kind that runs a size, set with mc_set_launch (the one-wave
+    kinds with the thresholds in LDS (0) or global memory (1), the lattice in
+    global memory (2), the pair (4) and quad (7) kernels; at the large sizes
+    the one-lane (5, 6) and quad (8, 9) streamed-row kernels with the table in
+    LDS or global memory), against the oracle over two rounds with a ragged
+    last workgroup."""
+    mc = _mc()
+    bs, M = 1, 3
+    w = _smooth_weight(L, bs, 90 + L)
+    for kind in kinds:
+        cpb = 16 if kind in (0, 1, 2, 4, 7, 9) else 32
+        ctx = mc.Context([(L, P, 4, bs)])
+        ctx.init_weights(w)
+        ctx.set_launch(kind, cpb)
+        assert ctx.launch()[:2] == (cpb, kind), (kind, ctx.launch())
+        R = O.Run(L, P, seed=4, bin_shift=bs, lnW=w)
+        for _ in range(2):
+            g = gpu_round(ctx, M)
+            o = oracle_round(R, M)
+            assert_round_equal(g, o)
+        assert_state_equal(ctx, R)
+        ctx.close()
