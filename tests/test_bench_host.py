@@ -56,3 +56,26 @@ def test_traffic_only_for_current_source_and_workload():
     assert t is None or t > 8e8
     assert bench.traffic_from_profiles(32, 4096, 99999) is None
     assert bench.traffic_from_profiles(16, 4096, 100000) is None
+
+
+def test_record_carries_the_contract_keys():
+    """The JSON line's keys and the roofline object's arithmetic, without a
+    GPU: frac = achieved / peak, achieved = ops per attempt x attempts / the
+    kernel's time, the peak from 256 CUs x 64 lanes x 2.4 GHz."""
+    import argparse
+
+    import bench
+
+    a = argparse.Namespace(steps=3, warmup=1)
+    rec = bench.base_record(a, 1.0e11, 3500.0, {"workload": "x"})
+    for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
+              "vs_baseline", "dtype", "data", "config"):
+        assert k in rec, k
+    assert rec["n_gpus"] == 1 and rec["vs_baseline"] is None and rec["config"]["workload"] == "x"
+    r = bench.roofline(4.194304e11, 3.5, 8.2e8)
+    for k in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
+        assert k in r, k
+    assert r["bound"] == "alu" and r["traffic"] == 8.2e8
+    assert abs(r["peak"] - 256 * 64 * 2.4e9 / 1e12) < 1e-9
+    assert abs(r["achieved"] - 31 * 4.194304e11 / 3.5 / 1e12) < 1e-9
+    assert abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-12
