@@ -467,3 +467,25 @@ def test_every_kernel_kind_bitexact(L, P, kinds):
             assert_round_equal(g, o)
         assert_state_equal(ctx, R)
         ctx.close()
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_one_sweep_rounds_bitexact(mode):
+    """Rounds of a single sweep (every trace holds one configuration, so each
+    cut point is 1 or -1) on the quad kernel, four rounds with an update after
+    each, in every joint mode (detailed balance in chain order, naive splice,
+    detailed balance in energy order), against the oracle."""
+    mc = _mc()
+    L, P, bs = 16, 50, 1
+    w = _smooth_weight(L, bs, 61)
+    ctx = mc.Context([(L, P, 6, bs)])
+    ctx.init_weights(w)
+    assert ctx.launch()[1] == 7
+    R = O.Run(L, P, seed=6, bin_shift=bs, lnW=w)
+    for _ in range(4):
+        g = gpu_round(ctx, 1, mode=mode)
+        o = oracle_round(R, 1, mode=mode)
+        assert_round_equal(g, o)
+        assert set(np.unique(g["cut"]).tolist()) <= {-1, 1}
+    assert_state_equal(ctx, R)
+    ctx.close()
