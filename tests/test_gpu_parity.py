@@ -489,3 +489,24 @@ def test_one_sweep_rounds_bitexact(mode):
         assert set(np.unique(g["cut"]).tolist()) <= {-1, 1}
     assert_state_equal(ctx, R)
     ctx.close()
+
+
+@pytest.mark.parametrize("L,kind", [(32, 7), (128, 8)])
+def test_single_chain_bitexact(L, kind):
+    """One chain: a workgroup with one of its 16 (or 32) chain slots used, and
+    joints that only ever test the chain against its own previous seam; three
+    rounds with updates in chain and energy order, against the oracle."""
+    mc = _mc()
+    bs = 1
+    w = _smooth_weight(L, bs, 62)
+    for mode in (0, 2):
+        ctx = mc.Context([(L, 1, 8, bs)])
+        ctx.init_weights(w)
+        assert ctx.launch()[1] == kind
+        R = O.Run(L, 1, seed=8, bin_shift=bs, lnW=w)
+        for _ in range(3):
+            g = gpu_round(ctx, 5, mode=mode)
+            o = oracle_round(R, 5, mode=mode)
+            assert_round_equal(g, o)
+        assert_state_equal(ctx, R)
+        ctx.close()
