@@ -1,30 +1,38 @@
 """Benchmark: parallel multicanonical Metropolis chains on the 2D Ising model
 (arXiv 0812.2964: Algorithm steps 2-5 and eq. new_weight) on one MI355X.
 
-Default workload (the one the headline metric is quoted on): L = 32, 4096
-chains x 10^5 sweeps per step, width-8 energy bins (513), the prior ln w of
-tests/golden/lnW_L32_prior.npy, seed 1.  One step = mc_run_chains (10^5 sweeps
-of every chain) + mc_join (detailed-balance joints over all 4096 chains) +
-mc_update_weights (eq. new_weight, flatness, re-tabulation).  Inputs are
+Default workload (the one the headline metric is quoted on): lattices of
+uneven size L in {16, 24, 32, 48, 64}, 2048 chains each, in one persistent
+launch; 10^5 sweeps per iteration, width-8 energy bins, ln w = 0 at the
+start, seed 1.  One step = one iteration of the recursion for all five sizes,
+replayed from a HIP graph: the sweeps of every chain (Algorithm step 2), the
+detailed-balance joints over each size's chains (steps 3-5) and the weight
+updates (eq. new_weight, flatness, re-tabulation).  The warmup steps are the
+recursion's first iterations, the timed steps the following ones; iterations
+to the first flat histogram are reported per size.  Inputs and state are
 resident in device memory before the timed region.
 
 Prints one JSON line with the throughput in spin-flip attempts/s, the sweep
-kernel against the integer-ALU roofline, and the CPU oracle timed on a
-bounded sample of the same workload.
+kernel against the integer-ALU roofline (and against the ceiling set by one
+wave's issue rate for serial chains), and the CPU oracle timed on a bounded
+sample of the same workload.
 
-Other workloads (--workload): recursion8 (L = 8, 16 chains, 10^4 sweeps, ten
-iterations from ln w = 0), batched (L = 16, 24, 32, 48, 64, 2048 chains each,
-graph-captured iterations), l128 (L = 128, 8192 chains; --lattice 100 or 256
-for the paper's size or the largest), thermo (the reduced
+Other workloads (--workload): l32 (L = 32, 4096 chains x 10^5 sweeps, the
+prior ln w fixture), recursion8 (L = 8, 16 chains, 10^4 sweeps, ten
+iterations from ln w = 0), large (L = 128, 8192 chains x 2 x 10^5 sweeps per
+iteration from ln w = 0, checkpointed across calls; --lattice 100 or 256),
+l128 (short runs of the large lattices for profiling), thermo (the reduced
 reweighting of code (ii) at L = 256 for 4096 inverse temperatures), fig2 (the
 comparison of Fig. 2: detailed-balance joints against naive splices at L = 20,
 measured by code (ii) against the exact energy), fig1 (the comparison of
 Fig. 1 at L = 64 and the paper's L = 100: weights from the learned
-initialiser, E, C, F, S of code (ii) against the exact finite lattice), topup (Algorithm step 6 with
-joints in chain order, in energy order and naive, at L = 20), learned
-(iterations to flat at L = 64 from the network's proposal against ln w = 0),
-and copy (a plain device copy of known size, to calibrate the HBM byte
-counters).
+initialiser, E, C, F, S of code (ii) against the exact finite lattice), topup
+(Algorithm step 6 with joints in chain order, in energy order and naive, at
+L = 20), learned (iterations to flat at L = 64 from the network's proposal
+against ln w = 0), learned256 (the network trained on converged weights of
+smaller lattices initialises L = 256, 4096 chains, against ln w = 0), peaks
+(the microbenchmarks of mc_probe) and copy (a plain device copy of known size,
+to calibrate the HBM byte counters).
 """
 import argparse
 import hashlib
@@ -39,13 +47,29 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Integer operations one Metropolis attempt needs, counted from the method:
+# Integer operations one Metropolis attempt needs, counted from the method as
+# two-operand operations (independent of any instruction set's fused forms):
 #   Philox4x32-10, one call per 4 words: 10 rounds x (2 mulhi + 2 mullo + 4 xor) = 80 -> 20 / attempt
 #   neighbour count (4 xor + 3 add), threshold index (1), compare (1), flip (1), level update (1) = 11
 OPS_PER_ATTEMPT = 31
-# MI355X: 256 CUs x 64 lanes x 2.4 GHz of full-rate 32-bit vector ALU operations.
-ALU_PEAK_OPS = 256 * 64 * 2.4e9
+# MI355X: 256 CUs x 128 lanes x 2.4 GHz of 32-bit vector ALU operations per
+# second (the published fp32 vector peak, 157.3 TFLOP/s, is 128 fused
+# multiply-adds per clock per CU; mc_probe measures 73-85 % of this figure for
+# v_xor_b32 and v_bitop3_b32 alone, so simple 32-bit integer operations run at
+# that width too, and 32-bit multiplies at about half of it).
+CLOCK_HZ = 2.4e9
+ALU_LANES_PER_CLK_PER_CU = 128
+ALU_PEAK_OPS = 256 * ALU_LANES_PER_CLK_PER_CU * CLOCK_HZ
 METRIC = "spin-flip attempts/s (multicanonical Ising, 1 GPU); iterations to flat H"
+BATCHED_LS = [16, 24, 32, 48, 64]
+# VALU instructions the consumer wave of a chain issues per step of four sites,
+# counted in the compiled code of the step (the instructions between two
+# selections of the quad's result in the unrolled row loop): the quad kernel
+# (kind 7, in the batched launch at L = 64 and alone at L = 32) and the
+# large-lattice quad kernel (kinds 8, 9 at L = 128).  A chain's attempts are
+# serial and its wave issues one VALU instruction per issue interval at best,
+# so 4 sites take at least valu_per_step x interval cycles.
+CONSUMER_VALU_PER_STEP = {7: 37, 8: 71, 9: 71}
 
 
 def log(msg):
@@ -57,9 +81,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="l32",
-                    choices=["l32", "recursion8", "batched", "l128", "thermo", "fig1", "fig2", "topup", "learned",
-                             "copy"])
+    ap.add_argument("--workload", default="batched",
+                    choices=["batched", "l32", "recursion8", "large", "l128", "thermo", "fig1", "fig2", "topup",
+                             "learned", "learned256", "peaks", "copy"])
     ap.add_argument("--rounds", type=int, default=None)
     ap.add_argument("--chains", type=int, default=None)
     ap.add_argument("--sweeps", type=int, default=None)
@@ -70,6 +94,11 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     ap.add_argument("--out-npz", default=None, help="fig1: also save the L = 64 and L = 100 weights there")
+    ap.add_argument("--metrics", default=None, help="write one JSON line of recursion statistics per iteration and "
+                                                      "size to this file")
+    ap.add_argument("--state-in", default=None, help="large: resume from this checkpoint")
+    ap.add_argument("--state-out", default=None, help="large: checkpoint to this file after every iteration")
+    ap.add_argument("--parts", type=int, default=4, help="large: launches per round (progress between them)")
     return ap.parse_args()
 
 
@@ -81,23 +110,76 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def traffic_from_profiles(L, P, M):
-    """HBM bytes per sweep launch from the committed counter summary, if it was
-    taken on the current kernel source and workload; else None."""
-    path = os.path.join(ROOT, "profiles", "k_sweep_pcq_L32_4096x1e5_counters.md")
+def traffic_from_profiles(name, workload):
+    """HBM bytes per sweep launch from the committed counter summary
+    profiles/<name>, if it was taken on the current kernel source and the
+    same workload (its "workload:" line); else None."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     txt = open(path).read()
     m_hash = re.search(r"kernel source sha256:\s*([0-9a-f]{64})", txt)
     m_bytes = re.search(r"HBM bytes per launch \(scaled\):\s*([0-9.eE+]+)", txt)
-    m_cfg = re.search(r"workload:\s*L=(\d+) chains=(\d+) sweeps=(\d+)", txt)
+    m_cfg = re.search(r"workload:[ \t]*([^\n]+)", txt)
     if not (m_hash and m_bytes and m_cfg):
         return None
-    if kernel_source_hash() != m_hash.group(1):
-        return None
-    if (int(m_cfg.group(1)), int(m_cfg.group(2)), int(m_cfg.group(3))) != (L, P, M):
+    if kernel_source_hash() != m_hash.group(1) or m_cfg.group(1).strip() != workload:
         return None
     return float(m_bytes.group(1))
+
+
+def issue_interval(mc):
+    """A lone wave's issue interval for independent VALU instructions
+    (mc_probe kind 8), in shader-clock cycles, and the shader clock the probe
+    saw (its cycles over its event time)."""
+    cyc, sec, _, cycles = mc.probe(8, 1 << 14)
+    return cyc, cycles / sec
+
+
+def chain_ceiling(mc, kinds, attempts_per_launch, serial_attempts):
+    """The ceiling serial chains put on one launch: the chain with the most
+    attempts (serial_attempts = sweeps x sites of the largest lattice) cannot
+    finish before its consumer wave has issued valu_per_step VALU
+    instructions per four sites, one per issue interval at best."""
+    kind = max(kinds, key=lambda k: CONSUMER_VALU_PER_STEP.get(k, 0))
+    if kind not in CONSUMER_VALU_PER_STEP:
+        return None
+    t, f = issue_interval(mc)
+    cycles_per_attempt = CONSUMER_VALU_PER_STEP[kind] * t / 4.0
+    launch_s = serial_attempts * cycles_per_attempt / CLOCK_HZ
+    return {"attempts_per_s": attempts_per_launch / launch_s, "valu_per_step": CONSUMER_VALU_PER_STEP[kind],
+            "sites_per_step": 4, "issue_cycles": t, "probe_clock_hz": f,
+            "cycles_per_attempt_floor": cycles_per_attempt, "kernel_kind": kind}
+
+
+def iteration_record(ctx, i, L, P, M, step, ms):
+    """One line of recursion statistics (mc_get_stats) for size i after an
+    iteration: retention, joints that kept nothing, cut points, flatness
+    ratio min h / mean h over the reachable bins, ln w span, step time."""
+    st = ctx.stats(i)
+    kept_chains = P - st["join_none"]
+    return {"L": L, "iteration": st["updates"], "step": step, "chains": P, "sweeps": M,
+            "retained_frac": st["retained_last"] / float(P * M), "n_no_accept": st["join_none"],
+            "mean_cut": st["join_cut_sum"] / kept_chains if kept_chains else None, "max_cut": st["join_cut_max"],
+            "flat_ratio": st["hist_min"] * st["n_reach_bins"] / float(st["hist_sum"]) if st["hist_sum"] else 0.0,
+            "flat": bool(st["last_flat"]), "first_flat": st["first_flat"] or None,
+            "lnW_span": st["lnw_max"] - st["lnw_min"], "step_ms": ms}
+
+
+class Metrics:
+    """Per-iteration JSON lines (--metrics), or nothing."""
+
+    def __init__(self, path):
+        self.f = open(path, "a") if path else None
+
+    def write(self, rec):
+        if self.f:
+            self.f.write(json.dumps(rec) + "\n")
+            self.f.flush()
+
+    def close(self):
+        if self.f:
+            self.f.close()
 
 
 def cpu_threads():
@@ -186,6 +268,9 @@ def bench_l32(a, torch, mc):
             ev.append((e0, e1))
         ctx.join(trace, cut, hist)
         ctx.update_weights(hist, want=False)
+        # the workload samples at the fixed prior weight: restore it after
+        # the update (which also clears the histogram for the next step)
+        ctx.init_weights(lnW)
 
     for w in range(a.warmup):
         step(False)
@@ -207,7 +292,8 @@ def bench_l32(a, torch, mc):
                                    "update), width-8 energy bins, prior ln w fixture, seed 1" % (L, P, M),
                        "L": L, "chains": P, "sweeps_per_step": M, "bins": ctx.n_bins(), "parallelism": "chains",
                        "chains_per_block": cpb, "kernel_kind": kind})
-    res["roofline"] = roofline(att, sweep_s, traffic_from_profiles(L, P, M))
+    res["roofline"] = roofline(att, sweep_s, traffic_from_profiles("k_sweep_pcq_L32_4096x1e5_counters.md",
+                                                                   "L=%d chains=%d sweeps=%d" % (L, P, M)))
     res["roofline"]["kernel"] = kernel_name(kind, L) + " (mc_run_chains)"
     res["sweep_attempts_per_s"] = att / sweep_s
     ctx.close()
@@ -240,47 +326,133 @@ def bench_recursion8(a, torch, mc):
     return res
 
 
+BATCHED_WORKLOAD = "L=16,24,32,48,64 chains=2048 sweeps=100000"
+
+
+def cpu_baseline_batched(Ls, lnWs, chains, sweeps):
+    """The oracle on the host for the batched workload's mix of sizes: one
+    thread running `chains` chains of every size for `sweeps` sweeps at the
+    weights the GPU reached, then every usable core, each thread running its
+    own block of `chains` chains of every size (keyed by the global chain
+    index, as a split run is), so that every thread does the same work.  The
+    value is the all-core rate; the single-thread rate is kept beside it."""
+    import threading
+
+    import oracle as O
+
+    def work(t):
+        for L, w in zip(Ls, lnWs):
+            O.Run(L, chains, seed=1, bin_shift=1, lnW=w, chain_offset=t * chains).run(sweeps, True)
+
+    per_thread = chains * sweeps * sum(L * L for L in Ls)
+    t0 = time.perf_counter()
+    work(0)
+    dt1 = time.perf_counter() - t0
+    T = cpu_threads()
+    threads = [threading.Thread(target=work, args=(t,)) for t in range(T)]
+    t0 = time.perf_counter()
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    dtT = time.perf_counter() - t0
+    return {"value": T * per_thread / dtT, "unit": "spin-flip attempts/s", "cores": T, "kind": "oracle",
+            "single_thread_value": per_thread / dt1,
+            "sample": "%d threads, each %d chains of every L in %s x %d sweeps at the weights the GPU reached "
+                      "(%.3g attempts, %.1f s); single thread: the same %d chains per L (%.1f s)"
+                      % (T, chains, Ls, sweeps, T * per_thread, dtT, chains, dt1)}
+
+
 def bench_batched(a, torch, mc):
-    Ls = [16, 24, 32, 48, 64]
+    """The batched workload: L in {16, 24, 32, 48, 64}, 2048 chains each, one
+    persistent launch per iteration, 10^5 sweeps, the recursion from
+    ln w = 0.  Each step replays a HIP graph of one whole iteration (sweeps,
+    joints, updates of every size); warmup steps are the first iterations."""
+    Ls = BATCHED_LS
     P = a.chains or 2048
     M = a.sweeps or 100000
-    iters = a.iters or 20
     sizes = [(L, P, 1, 1) for L in Ls]
-    ctx = mc.Context(sizes)
-    log("bench batched: autotuning")
+    stream = torch.cuda.current_stream()
+    ctx = mc.Context(sizes, stream=stream)
+    log("bench batched: L=%s, %d chains each, %d sweeps per iteration; autotuning" % (Ls, P, M))
     cpbs = ctx.autotune(200)
+    plans = [ctx.launch(i) for i in range(len(Ls))]
+    log("bench batched: plans (chains per workgroup, kind, batched) %s" % plans)
     trs = [ctx.new_trace(M, i) for i in range(len(Ls))]
     hs = [ctx.new_hist(i) for i in range(len(Ls))]
     cuts = [ctx.new_cut(i) for i in range(len(Ls))]
     g = ctx.graph(M, 1, trs, hs, cuts)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for it in range(iters):
+    metrics = Metrics(a.metrics)
+    ev = []
+    elapsed = 0.0
+    for s in range(a.warmup + a.steps):
+        timed = s >= a.warmup
+        if s == a.warmup:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
         g.launch()
+        e1.record(stream)
         torch.cuda.synchronize()
-        log("bench batched: iteration %d done (%.1f s)" % (it + 1, time.perf_counter() - t0))
-    dt = time.perf_counter() - t0
-    flats = {L: ctx.progress(i)[1] or None for i, L in enumerate(Ls)}
-    att = iters * P * M * sum(L * L for L in Ls)
+        ms = e0.elapsed_time(e1)
+        if timed:
+            ev.append(ms)
+            elapsed = time.perf_counter() - t0
+        for i, L in enumerate(Ls):
+            metrics.write(iteration_record(ctx, i, L, P, M, s + 1, ms))
+        log("bench batched: %s step %d done (%.0f ms%s)" % ("timed" if timed else "warmup", s + 1, ms,
+                                                          ", %.1f s so far" % elapsed if timed else ""))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    metrics.close()
+    flats = {str(L): ctx.progress(i)[1] or None for i, L in enumerate(Ls)}
+    iters_run = ctx.progress(0)[0]
+    weights = [ctx.weights(i) for i in range(len(Ls))]
+    att = P * M * sum(L * L for L in Ls)
     g.close()
     ctx.close()
-    res = base_record(a, att / dt, dt / iters * 1e3,
-                      {"workload": "batched L in {16,24,32,48,64}, %d chains each x %d sweeps, %d graph-captured "
-                                   "iterations from ln w = 0, one persistent launch" % (P, M, iters),
-                       "L": Ls, "chains_per_L": P, "sweeps_per_iter": M, "iterations": iters,
-                       "chains_per_block": cpbs})
+    launch_s = sum(ev) / len(ev) / 1e3
+    res = base_record(a, a.steps * att / elapsed, elapsed / a.steps * 1e3,
+                      {"workload": "batched uneven L in {16,24,32,48,64}, %d chains each x %d sweeps per iteration "
+                                   "in one persistent launch, width-8 energy bins, recursion from ln w = 0, seed 1; "
+                                   "one step = one HIP-graph-captured iteration (sweeps + joints + weight updates of "
+                                   "every size)" % (P, M),
+                       "L": Ls, "chains_per_L": P, "sweeps_per_iter": M, "parallelism": "chains",
+                       "chains_per_block": cpbs, "kernel_kinds": [p_[1] for p_ in plans]})
+    res["roofline"] = roofline(att, launch_s, traffic_from_profiles("k_sweep_batched_5L_2048x1e5_counters.md",
+                                                                    BATCHED_WORKLOAD))
+    res["roofline"]["kernel"] = "k_sweep_batched (mc_run_chains, one persistent launch of the five sizes)"
+    res["roofline"]["kernel_ms_basis"] = ("HIP events around each graph replay on the context's stream: the sweep "
+                                          "launch plus the joints and updates of the five sizes (a few ms)")
+    cc = chain_ceiling(mc, [p_[1] for p_ in plans], att, M * max(Ls) ** 2)
+    if cc is not None:
+        cc["frac"] = (att / launch_s) / cc["attempts_per_s"]
+        res["roofline"]["chain_ceiling"] = cc
+    res["sweep_attempts_per_s"] = att / launch_s
+    res["iterations_run"] = iters_run
     res["iterations_to_flat"] = flats
+    if not a.no_cpu:
+        log("bench batched: timing the CPU oracle on a sample")
+        res["cpu_baseline"] = cpu_baseline_batched(Ls, weights, 4, a.cpu_sweeps // 2)
     return res
 
 
 def bench_l128(a, torch, mc):
+    """Short runs of a large lattice (--lattice 100, 128 or 256), 8192
+    chains x --sweeps (1000) sweeps per step from ln w = 0, for profiling; the
+    value is the whole step's rate (run + joint + update)."""
     L, P = a.lattice, a.chains or 8192
     M = a.sweeps or 1000
-    ctx = mc.Context([(L, P, 1, 1)])
-    trace, hist, cut = ctx.new_trace(M), ctx.new_hist(), ctx.new_cut()
     stream = torch.cuda.current_stream()
+    ctx = mc.Context([(L, P, 1, 1)], stream=stream)
+    trace, hist, cut = ctx.new_trace(M), ctx.new_hist(), ctx.new_cut()
     times = []
+    t0 = None
     for s in range(a.warmup + a.steps):
+        if s == a.warmup:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         ctx.run_chains(M, trace, hist)
@@ -291,15 +463,233 @@ def bench_l128(a, torch, mc):
         if s >= a.warmup:
             times.append(e0.elapsed_time(e1) / 1e3)
         log("bench l128 (L=%d): step %d done" % (L, s + 1))
+    elapsed = time.perf_counter() - t0
     att = P * M * L * L
     sweep_s = sum(times) / len(times)
     cpb, kind, _ = ctx.launch()
     ctx.close()
-    res = base_record(a, att / sweep_s, sweep_s * 1e3,
-                      {"workload": "2D Ising L=%d, %d chains x %d sweeps per step, ln w = 0 start" % (L, P, M),
+    res = base_record(a, a.steps * att / elapsed, elapsed / a.steps * 1e3,
+                      {"workload": "2D Ising L=%d, %d chains x %d sweeps per step (run + joint + update), ln w = 0 "
+                                   "start" % (L, P, M),
                        "L": L, "chains": P, "sweeps_per_step": M, "kernel_kind": kind})
     res["roofline"] = roofline(att, sweep_s, None)
     res["roofline"]["kernel"] = kernel_name(kind, L) + " (mc_run_chains)"
+    res["sweep_attempts_per_s"] = att / sweep_s
+    return res
+
+
+def bench_large(a, torch, mc):
+    """The large-lattice recursion: L = 128 (--lattice), 8192 chains x
+    2 x 10^5 sweeps per iteration, from ln w = 0, up to --iters iterations in
+    all (40), --steps of them in this call.  Each round is made in --parts
+    launches (mc_run_chains_part) with a progress line after each; then the
+    joint, the update and the level check (mc_check_levels).  The state is
+    checkpointed after every iteration (--state-out) and a later call resumes
+    it (--state-in), so the record spans several calls.  The line reports
+    this call's iterations; --metrics collects one line per iteration."""
+    L = a.lattice
+    P = a.chains or 8192
+    M = a.sweeps or 200000
+    cap = a.iters or 40
+    parts = max(1, a.parts)
+    if M % parts:
+        raise SystemExit("--sweeps must be a multiple of --parts")
+    N = L * L
+    stream = torch.cuda.current_stream()
+    ctx = mc.Context([(L, P, 1, 1)], stream=stream)
+    if a.state_in:
+        with open(a.state_in, "rb") as f:
+            ctx.set_state(f.read())
+    done0 = ctx.stats()["updates"]
+    todo = min(a.steps, cap - done0)
+    cpb, kind, _ = ctx.launch()
+    log("bench large: L=%d chains=%d sweeps=%d in %d parts; %d iterations done, %d to run (cap %d); kind %d, "
+        "%d chains per workgroup" % (L, P, M, parts, done0, todo, cap, kind, cpb))
+    trace, hist, cut = ctx.new_trace(M), ctx.new_hist(), ctx.new_cut()
+    metrics = Metrics(a.metrics)
+    sweep_ms, step_s, flat_ratio = [], [], []
+    t_all = time.perf_counter()
+    for it in range(todo):
+        t0 = time.perf_counter()
+        ms = 0.0
+        for k in range(parts):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            ctx.run_chains_part(M // parts, k * (M // parts), trace, hist)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms += e0.elapsed_time(e1)
+            log("bench large: iteration %d, sweeps %d of %d (%.0f s)" % (done0 + it + 1, (k + 1) * (M // parts), M,
+                                                                          time.perf_counter() - t0))
+        ctx.join(trace, cut, hist)
+        ctx.update_weights(hist, want=False)
+        ctx.check_levels()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        sweep_ms.append(ms)
+        step_s.append(dt)
+        rec = iteration_record(ctx, 0, L, P, M, done0 + it + 1, dt * 1e3)
+        rec["sweep_ms"] = ms
+        metrics.write(rec)
+        flat_ratio.append(rec["flat_ratio"])
+        if a.state_out:
+            blob = ctx.get_state()
+            with open(a.state_out + ".tmp", "wb") as f:
+                f.write(blob)
+            os.replace(a.state_out + ".tmp", a.state_out)
+        log("bench large: iteration %d done in %.1f s: flat_ratio %.3g, kept %.3f, lnW span %.1f%s"
+            % (rec["iteration"], dt, rec["flat_ratio"], rec["retained_frac"], rec["lnW_span"],
+               ", FLAT" if rec["flat"] else ""))
+        if rec["first_flat"]:
+            break
+    metrics.close()
+    st = ctx.stats()
+    ctx.close()
+    att = P * M * N
+    n = len(sweep_ms)
+    elapsed = time.perf_counter() - t_all
+    res = base_record(a, n * att / max(elapsed, 1e-9), elapsed / max(n, 1) * 1e3,
+                      {"workload": "2D Ising L=%d, %d chains x %d sweeps per iteration, recursion from ln w = 0 to "
+                                   "a flat histogram (min h >= 0.8 mean over reachable bins) within %d iterations, "
+                                   "width-8 bins, seed 1; iterations %d..%d of the record in this call"
+                                   % (L, P, M, cap, done0 + 1, done0 + n),
+                       "L": L, "chains": P, "sweeps_per_iter": M, "cap": cap, "kernel_kind": kind,
+                       "chains_per_block": cpb})
+    res["steps"] = n
+    res["warmup"] = 0
+    if n:
+        sweep_s = sum(sweep_ms) / n / 1e3
+        res["roofline"] = roofline(att, sweep_s, None)
+        res["roofline"]["kernel"] = kernel_name(kind, L) + " (mc_run_chains_part, %d launches per round)" % parts
+        res["sweep_attempts_per_s"] = att / sweep_s
+    res["iterations_done"] = st["updates"]
+    res["iterations_to_flat"] = st["first_flat"] or None
+    res["flat_ratio_this_call"] = flat_ratio
+    return res
+
+
+def bench_learned256(a, torch, mc):
+    """The learned initialiser at L = 256: the network is trained on converged
+    weights of L = 8, 16, 32 (recursions from ln w = 0) and 64 (the
+    network's own proposal run to flat), then proposes ln w for L = 256;
+    4096 chains x --sweeps (2000) sweeps per iteration run from the proposal
+    and from ln w = 0 for at most --iters (40) iterations each.  Reported:
+    iterations to flat (or none within the cap), the flatness ratio per
+    iteration, the difference between the two arms' final ln w, and code
+    (ii)'s E, C, F, S of both against Kaufman's exact L = 256 torus."""
+    from paper_0812_2964_amd.learned import Initializer, relative_spread, run_to_flat
+    import mpmath
+    from paper_0812_2964_amd import exact as X
+
+    P, M = a.chains or 4096, a.sweeps or 2000
+    cap = a.iters or 40
+    Lt = 256
+    Nt = Lt * Lt
+    t0 = time.perf_counter()
+    ini = Initializer(seed=1)
+    stages = {}
+    for L, c in [(8, 60), (16, 200), (32, 400)]:
+        w, flat, done = run_to_flat(L, P, M, c, extra=4)
+        stages[L] = {"from": "ln w = 0", "first_flat": flat, "iterations": done}
+        if flat is not None:
+            ini.add(L, w)
+        log("bench learned256: L = %d flat at %s (%.0f s)" % (L, flat, time.perf_counter() - t0))
+    ini.fit(steps=4000, lr=2e-3)
+    w64, flat, done = run_to_flat(64, P, M, 400, lnW0=ini.predict(64), extra=4)
+    stages[64] = {"from": "network (8, 16, 32)", "first_flat": flat, "iterations": done}
+    if flat is not None:
+        ini.add(64, w64)
+    loss = ini.fit(steps=4000, lr=2e-3)
+    log("bench learned256: L = 64 flat at %s; trained on %s (loss %.3g, %.0f s)"
+        % (flat, [k for k, v in stages.items() if v["first_flat"]], loss, time.perf_counter() - t0))
+    metrics = Metrics(a.metrics)
+    arms = {}
+    finals = {}
+    for name, lnW0 in [("learned", ini.predict(Lt)), ("plain", None)]:
+        ctx = mc.Context([(Lt, P, 1, 1)])
+        ctx.init_weights(lnW0)
+        tr, h, cut = ctx.new_trace(M), ctx.new_hist(), ctx.new_cut()
+        t1 = time.perf_counter()
+        ratios = []
+        for it in range(cap):
+            ctx.run_chains(M, tr, h)
+            ctx.join(tr, cut, h)
+            ctx.update_weights(h, want=False)
+            rec = iteration_record(ctx, 0, Lt, P, M, it + 1, 0.0)
+            rec["arm"] = name
+            metrics.write(rec)
+            ratios.append(rec["flat_ratio"])
+            log("bench learned256: %s iteration %d: flat_ratio %.3g, lnW span %.0f (%.0f s)"
+                % (name, it + 1, rec["flat_ratio"], rec["lnW_span"], time.perf_counter() - t1))
+            if rec["first_flat"]:
+                break
+        st = ctx.stats()
+        finals[name] = ctx.weights()
+        betas = np.round(np.concatenate([np.arange(0.1, 0.375, 0.05), np.arange(0.40, 0.475, 0.01),
+                                         np.arange(0.5, 1.01, 0.1)]), 4)
+        e, c, f, s_ = ctx.thermo(betas)
+        ctx.close()
+        arms[name] = {"iterations_to_flat": st["first_flat"] or None, "iterations_run": st["updates"],
+                      "seconds": time.perf_counter() - t1, "flat_ratio": ratios,
+                      "thermo": {"beta": betas.tolist(), "E": (e / Nt).tolist(), "C": (c / Nt).tolist(),
+                                 "F": (f / Nt).tolist(), "S": (s_ / Nt).tolist()}}
+    metrics.close()
+    # Kaufman's exact finite-lattice values at the same inverse temperatures
+    ex = {"E": [], "C": [], "F": [], "S": []}
+    betas = arms["learned"]["thermo"]["beta"]
+    with mpmath.workprec(300):
+        hh = mpmath.mpf("1e-30")
+        for b in betas:
+            bb = mpmath.mpf(float(b))
+            z0, zp, zm = X.kaufman_lnZ(Lt, bb), X.kaufman_lnZ(Lt, bb + hh), X.kaufman_lnZ(Lt, bb - hh)
+            E = -(zp - zm) / (2 * hh)
+            ex["E"].append(float(E) / Nt)
+            ex["C"].append(float(bb * bb * (zp - 2 * z0 + zm) / (hh * hh)) / Nt)
+            ex["F"].append(float(-z0 / bb) / Nt)
+            ex["S"].append(float(bb * E + z0) / Nt)
+    for name in arms:
+        th = arms[name]["thermo"]
+        arms[name]["max_abs_dev_per_site"] = {k: float(np.max(np.abs(np.array(th[k]) - np.array(ex[k])))) for k in ex}
+    sec = sum(v["seconds"] for v in arms.values())
+    att = sum(v["iterations_run"] for v in arms.values()) * P * M * Nt
+    res = base_record(a, att / sec, sec / max(1, sum(v["iterations_run"] for v in arms.values())) * 1e3,
+                      {"workload": "learned initial weight for L=256, 4096 chains x %d sweeps per iteration, width-8 "
+                                   "bins, seed 1, cap %d iterations per arm; network trained on converged ln w of "
+                                   "L=8, 16, 32, 64" % (M, cap), "L": Lt, "chains": P, "sweeps_per_iter": M,
+                       "cap": cap})
+    res["training"] = {"stages": {str(k): v for k, v in stages.items()}, "loss": loss}
+    res["arms"] = arms
+    res["exact_per_site"] = ex
+    res["iterations_to_flat"] = {k: v["iterations_to_flat"] for k, v in arms.items()}
+    res["final_lnW_spread_between_arms"] = relative_spread(finals["learned"], finals["plain"])
+    return res
+
+
+def bench_peaks(a, torch, mc):
+    """The microbenchmarks of mc_probe: chip-wide VALU rates of the attempt's
+    instruction classes, LDS bandwidth, dependent LDS read latency and a lone
+    wave's issue interval."""
+    iters = {0: 4096, 1: 4096, 2: 4096, 3: 2048, 4: 4096, 5: 8192, 6: 1 << 14, 7: 1 << 14, 8: 1 << 14}
+    out = {}
+    for k, name in mc.PROBES.items():
+        fig, sec, work, cyc = mc.probe(k, iters[k])
+        out[name] = {"value": fig, "seconds": sec, "work": work, "cycles": cyc}
+        log("bench peaks: %s = %.4g (%.3f ms)" % (name, fig, sec * 1e3))
+    res = base_record(a, out["valu_xor"]["value"], out["valu_xor"]["seconds"] * 1e3,
+                      {"workload": "mc_probe microbenchmarks (chip-wide VALU rates, LDS bandwidth and latency, "
+                                   "lone-wave issue interval)"})
+    res["metric"] = "32-bit VALU lane-instructions/s (v_xor_b32), with the other probes beside it"
+    res["unit"] = "lane-instructions/s"
+    res["probes"] = out
+    res["derived"] = {
+        "valu_peak_spec": ALU_PEAK_OPS,
+        "valu_xor_frac_of_spec": out["valu_xor"]["value"] / ALU_PEAK_OPS,
+        "mul_lo_rate_vs_xor": out["valu_mul_lo"]["value"] / out["valu_xor"]["value"],
+        "mul_hi_rate_vs_xor": out["valu_mul_hi"]["value"] / out["valu_xor"]["value"],
+        "mad_u64_rate_vs_xor": out["valu_mad_u64"]["value"] / out["valu_xor"]["value"],
+        "lds_bytes_per_clk_per_cu": out["lds_read_bandwidth"]["value"] / (256 * CLOCK_HZ),
+        "shader_clock_hz_seen_by_lone_wave_probe": out["lone_wave_independent_issue_cycles"]["cycles"]
+                                                   / out["lone_wave_independent_issue_cycles"]["seconds"]}
     return res
 
 
@@ -360,8 +750,7 @@ def bench_fig2(a, torch, mc):
     32 chains x 100 sweeps (M_node), joined after every round (Algorithm
     step 6), before the weight update; one bin per level, so that the energy
     resolution of the weight is that of the model."""
-    sys.path.insert(0, os.path.join(ROOT, "tests"))
-    import exact_ising as X
+    from paper_0812_2964_amd import exact as X
 
     L, P, M = 20, a.chains or 32, a.sweeps or 100
     N = L * L
@@ -421,8 +810,7 @@ def bench_topup(a, torch, mc):
     (mode 1) are compared by retention, rounds and sweeps per iteration,
     iterations to the first flat histogram and the energy of code (ii) against
     Kaufman's exact energy of the 20 x 20 torus."""
-    sys.path.insert(0, os.path.join(ROOT, "tests"))
-    import exact_ising as X
+    from paper_0812_2964_amd import exact as X
 
     L, P, M = 20, a.chains or 32, a.sweeps or 100
     N = L * L
@@ -484,9 +872,8 @@ def bench_fig1(a, torch, mc):
     and its proposal for L = 100 is run to flat (at most --iters
     iterations)."""
     from paper_0812_2964_amd.learned import Initializer, run_to_flat
-    sys.path.insert(0, os.path.join(ROOT, "tests"))
     import mpmath
-    import exact_ising as X
+    from paper_0812_2964_amd import exact as X
 
     P, M = a.chains or 4096, a.sweeps or 2000
     P_big = 8192
@@ -634,6 +1021,12 @@ def main():
         res = bench_batched(a, torch, mc)
     elif a.workload == "l128":
         res = bench_l128(a, torch, mc)
+    elif a.workload == "large":
+        res = bench_large(a, torch, mc)
+    elif a.workload == "learned256":
+        res = bench_learned256(a, torch, mc)
+    elif a.workload == "peaks":
+        res = bench_peaks(a, torch, mc)
     elif a.workload == "thermo":
         res = bench_thermo(a, torch, mc)
     elif a.workload == "fig2":
@@ -644,8 +1037,10 @@ def main():
         res = bench_fig1(a, torch, mc)
     elif a.workload == "learned":
         res = bench_learned(a, torch, mc)
-    else:
+    elif a.workload == "l32":
         res = bench_l32(a, torch, mc)
+    else:
+        res = bench_batched(a, torch, mc)
     print(json.dumps(res), flush=True)
 
 

@@ -60,7 +60,8 @@ typedef enum {
     MC_EHIP = -4,       /* a HIP runtime call failed; the context is broken   */
     MC_ESTATE = -5,     /* call out of order (e.g. join of sweeps not run)    */
     MC_EOVERFLOW = -6,  /* histogram or counter range would be exceeded       */
-    MC_ECORRUPT = -7    /* a state blob failed its checks                     */
+    MC_ECORRUPT = -7,   /* a state blob failed its checks                     */
+    MC_EINTERNAL = -8   /* the chain state failed a consistency check         */
 } mc_status;
 
 /* One lattice size of a context.  Sizes are independent ensembles: each has
@@ -112,8 +113,26 @@ mc_status mc_init_weights(mc_ctx *ctx, int32_t size_idx, const double *lnW_host,
                    joint histogram so far, on entry).
    trace_dev and hist_dev are host arrays of n_sizes device pointers.
    Errors: MC_EINVAL (n_sweeps < 1, NULL pointer), MC_EOVERFLOW (more than
-   2^31-1 configurations would be counted before the next weight update). */
+   2^31-1 configurations would be counted before the next weight update, or
+   the size's sweeps would pass 2^32 in its lifetime: the sweep index is a
+   32-bit counter of the random words, which would then repeat). */
 mc_status mc_run_chains(mc_ctx *ctx, int64_t n_sweeps, void *const *trace_dev, int32_t *const *hist_dev);
+
+/* Algorithm step 2 for one round of row_len sweeps made in several launches
+   (progress reports between launches, bounded kernel durations): n_sweeps
+   more sweeps of every chain, written to columns
+   col .. col + n_sweeps - 1 of each size's [n_chains][row_len] trace
+   (trace_dev[s] is the start of that trace, not of the columns).  The
+   chains, random words and histogram are exactly those of one
+   mc_run_chains(row_len) call: the parts of a round are bit for bit the
+   whole.  col = 0 starts a round; each later part must continue it (col =
+   sweeps made so far, the same row_len).  The round can be joined
+   (mc_join with n_sweeps = row_len) once col + n_sweeps = row_len.
+   mc_run_chains(ctx, n, t, h) is mc_run_chains_part(ctx, n, 0, n, t, h).
+   Errors: as mc_run_chains; MC_EINVAL when the columns do not fit the rows;
+   MC_ESTATE for a part that does not continue the round in progress. */
+mc_status mc_run_chains_part(mc_ctx *ctx, int64_t n_sweeps, int64_t col, int64_t row_len, void *const *trace_dev,
+                             int32_t *const *hist_dev);
 
 /* Algorithm steps 3-5 for one size over the trace of the last mc_run_chains
    (n_sweeps must match it).  For chain i = 0 .. n_chains-1 in order, the
@@ -138,7 +157,9 @@ mc_status mc_run_chains(mc_ctx *ctx, int64_t n_sweeps, void *const *trace_dev, i
                first and last columns and synchronises.
    The test of chain c's k-th configuration uses its own random word (round,
    c, k) in every mode, whatever c's position.
-   Errors: MC_EINVAL, MC_ESTATE (no matching mc_run_chains). */
+   Errors: MC_EINVAL, MC_ESTATE (no complete round of mc_run_chains to join),
+   MC_EOVERFLOW (the size's 2^32 joint rounds, a 32-bit counter of the
+   random words, are used up). */
 mc_status mc_join(mc_ctx *ctx, int32_t size_idx, const void *trace_dev, int64_t n_sweeps, int32_t *cut_dev,
                   int32_t *hist_dev, int32_t mode);
 
@@ -206,7 +227,7 @@ mc_status mc_set_seam(mc_ctx *ctx, int32_t size_idx, int32_t seam);
    and mc_update_weights resumes only together with the caller's histogram.
    mc_get_state: with buf NULL, *len receives the size; otherwise buf must
    hold *len >= that size, and *len receives it.  MC_EINVAL for a null len or
-   a short buffer.
+   a short buffer; MC_ESTATE while a round is partly run (mc_run_chains_part).
    mc_set_state: the context must have been created with the same sizes,
    chain counts, seeds and bins (MC_EINVAL otherwise).  A blob that fails its
    magic, version, length or checksum, holds a non-finite ln w, counters out of
@@ -299,7 +320,9 @@ mc_status mc_autotune(mc_ctx *ctx, int64_t probe_sweeps, int32_t *chains_per_blo
    zeros before the first replay (each update leaves them zeroed).  A graph
    can only be created and launched right after a weight update (or at the
    start).  Destroy graphs before their context.
-   Errors: MC_EINVAL, MC_ESTATE, MC_EOVERFLOW (n_chains * n_sweeps >= 2^31). */
+   Errors: MC_EINVAL, MC_ESTATE, MC_EOVERFLOW (n_chains * n_sweeps >= 2^31;
+   at launch, also when a replay would pass the 2^32 sweep or joint-round
+   counters of the random words). */
 typedef struct mc_graph mc_graph;
 mc_status mc_graph_create(mc_ctx *ctx, int64_t n_sweeps, int32_t n_iters, void *const *trace_dev,
                           int32_t *const *hist_dev, int32_t *const *cut_dev, int32_t mode, mc_graph **out);
@@ -346,6 +369,58 @@ mc_status mc_mlp_targets(const double *lnW_dev, int32_t L, int32_t bin_shift, fl
 /* Proposed ln w of a lattice size: lnW_dev [n_bins] = -N f(1/L, e_b). */
 mc_status mc_mlp_predict_weights(const float *params_dev, int32_t L, int32_t bin_shift, double *lnW_dev,
                                  void *hip_stream);
+
+/* Statistics of one size for a record of the recursion (synchronising):
+   the progress of mc_get_progress, the histogram of the last weight update
+   over the bins that hold a reachable level (its total, its smallest bin --
+   flatness is 5 n_reach_bins hist_min >= 4 hist_sum -- and the number of such
+   bins), the range of ln w over those bins after that update, the last
+   joint's chains that kept nothing, its largest cut point and the sum of its
+   cut points over the chains that kept something (Algorithm steps 3-5), and
+   the device counters (next sweep index, next joint round, seam). */
+typedef struct {
+    int32_t updates, first_flat, last_flat;
+    int32_t n_reach_bins;
+    int64_t retained_last;
+    int64_t hist_sum, hist_min;
+    double lnw_min, lnw_max;
+    int32_t join_none, join_cut_max;
+    int64_t join_cut_sum;
+    uint32_t sweep_index, round_index;
+    int32_t seam;
+} mc_stats;
+mc_status mc_get_stats(mc_ctx *ctx, int32_t size_idx, mc_stats *out);
+
+/* Consistency check of the chains of one size (synchronising): the sweeps
+   track each chain's level m = (E + 2N)/4 incrementally (Sec. 4.1, J = 1,
+   E = -sum of s_i s_j over the 2N bonds), so each level must equal half the
+   number of broken bonds of the chain's lattice.  A kernel recounts them.
+   *n_bad (nullable) receives the number of chains that disagree.  Returns
+   MC_OK, or MC_EINTERNAL if any chain disagrees (the state is corrupt, by a
+   fault of the library or of memory). */
+mc_status mc_check_levels(mc_ctx *ctx, int32_t size_idx, int64_t *n_bad);
+
+/* Microbenchmarks of the chip resources that bound the sweep kernels (a
+   measurement, not a step of the method; no context).  The method's work is
+   integer vector ALU work on strictly serial chains, so the roofline of the
+   sweeps is set by the ALU rate of its instruction classes, by LDS, and by
+   what one wave issues.  kind:
+     0..4  chip-wide rate of independent 32-bit VALU instructions, in
+           lane-instructions/s: 0 v_xor_b32, 1 v_mul_lo_u32, 2 v_mul_hi_u32,
+           3 v_mad_u64_u32 (the Philox multiply), 4 v_bitop3_b32 (three-input
+           xor); 8 one-wave workgroups per SIMD;
+     5     chip-wide LDS read bandwidth, bytes/s (16-byte reads, no bank
+           conflicts, two 256-thread workgroups per compute unit);
+     6     latency of one wave's dependent LDS reads, shader-clock cycles per
+           read (including the one instruction that forms the next address);
+     7, 8  issue interval of a lone wave, cycles per instruction, for
+           dependent (7) and independent (8) simple VALU instructions.
+   iters (1..2^24) scales the work.  out_host[4]: the figure, the seconds of
+   the timed launch (hipEvents), the work counted (lane-instructions, bytes,
+   reads or instructions), the shader-clock cycles counted (kinds 6..8).
+   Allocates and frees its own device buffers; synchronises hip_stream.
+   Errors: MC_EINVAL, MC_ENODEV, MC_ENOMEM, MC_EHIP. */
+mc_status mc_probe(int32_t kind, int32_t iters, void *hip_stream, double *out_host);
 
 /* Wait for all work of the context. */
 mc_status mc_sync(mc_ctx *ctx);

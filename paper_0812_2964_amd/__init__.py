@@ -15,9 +15,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmcgpu.so")
 
-MC_OK, MC_EINVAL, MC_ENOMEM, MC_ENODEV, MC_EHIP, MC_ESTATE, MC_EOVERFLOW, MC_ECORRUPT = 0, -1, -2, -3, -4, -5, -6, -7
+MC_OK, MC_EINVAL, MC_ENOMEM, MC_ENODEV, MC_EHIP, MC_ESTATE, MC_EOVERFLOW, MC_ECORRUPT, MC_EINTERNAL = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8
 _STATUS = {0: "MC_OK", -1: "MC_EINVAL", -2: "MC_ENOMEM", -3: "MC_ENODEV", -4: "MC_EHIP", -5: "MC_ESTATE",
-           -6: "MC_EOVERFLOW", -7: "MC_ECORRUPT"}
+           -6: "MC_EOVERFLOW", -7: "MC_ECORRUPT", -8: "MC_EINTERNAL"}
 
 # Symbols declared in include/mc.h (checked by the CPU test-suite).
 EXPORTED = ["mc_create", "mc_destroy", "mc_n_bins", "mc_trace_elem_bytes", "mc_lattice_words", "mc_init_weights",
@@ -26,13 +27,27 @@ EXPORTED = ["mc_create", "mc_destroy", "mc_n_bins", "mc_trace_elem_bytes", "mc_l
             "mc_graph_create", "mc_graph_launch", "mc_graph_destroy", "mc_sync", "mc_last_error",
             "mc_mlp_n_params", "mc_mlp_workspace_bytes", "mc_mlp_init", "mc_mlp_forward", "mc_mlp_loss_grad",
             "mc_mlp_train", "mc_mlp_targets", "mc_mlp_predict_weights", "mc_thermo", "mc_iterate_topup",
-            "mc_get_state", "mc_set_state", "mc_set_seam"]
+            "mc_get_state", "mc_set_state", "mc_set_seam", "mc_run_chains_part", "mc_get_stats", "mc_check_levels",
+            "mc_probe"]
 
 
 class MCError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__("%s: %s" % (_STATUS.get(status, status), msg))
         self.status = status
+
+
+class Stats(ctypes.Structure):
+    """mc_stats: progress, the last update's histogram and ln w range, the
+    last joint's cut statistics and the device counters of one size."""
+    _fields_ = [("updates", ctypes.c_int32), ("first_flat", ctypes.c_int32), ("last_flat", ctypes.c_int32),
+                ("n_reach_bins", ctypes.c_int32), ("retained_last", ctypes.c_int64), ("hist_sum", ctypes.c_int64),
+                ("hist_min", ctypes.c_int64), ("lnw_min", ctypes.c_double), ("lnw_max", ctypes.c_double),
+                ("join_none", ctypes.c_int32), ("join_cut_max", ctypes.c_int32), ("join_cut_sum", ctypes.c_int64),
+                ("sweep_index", ctypes.c_uint32), ("round_index", ctypes.c_uint32), ("seam", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class _Size(ctypes.Structure):
@@ -61,6 +76,10 @@ def lib():
         getattr(L, f).restype = i32
     L.mc_init_weights.argtypes = [p, i32, p, i32]
     L.mc_run_chains.argtypes = [p, i64, p, p]
+    L.mc_run_chains_part.argtypes = [p, i64, i64, i64, p, p]
+    L.mc_get_stats.argtypes = [p, i32, ctypes.POINTER(Stats)]
+    L.mc_check_levels.argtypes = [p, i32, ctypes.POINTER(i64)]
+    L.mc_probe.argtypes = [i32, i32, p, p]
     L.mc_join.argtypes = [p, i32, p, i64, p, p, i32]
     L.mc_update_weights.argtypes = [p, i32, p, p, p, p]
     L.mc_iterate_topup.argtypes = [p, i64, i64, i32, p, p, p, i32, p, p, p, p]
@@ -201,6 +220,27 @@ class Context:
             hp[i] = _dev_ptr(hists[i], torch.int32, self.n_bins(i), "hist").value
         _check(lib().mc_run_chains(self._h, int(n_sweeps), tp, hp))
 
+    def run_chains_part(self, n_sweeps, col, traces, hists):
+        """Sweeps n_sweeps more of a round whose traces (one [n_chains][row_len]
+        tensor per size) are filled from column col (mc_run_chains_part)."""
+        import torch
+
+        if isinstance(traces, torch.Tensor):
+            traces = [traces]
+        if isinstance(hists, torch.Tensor):
+            hists = [hists]
+        if len(traces) != len(self.sizes) or len(hists) != len(self.sizes):
+            raise ValueError("need one trace and one hist per size")
+        row_len = traces[0].shape[-1]
+        tp = (ctypes.c_void_p * len(self.sizes))()
+        hp = (ctypes.c_void_p * len(self.sizes))()
+        for i in range(len(self.sizes)):
+            if traces[i].shape[-1] != row_len:
+                raise ValueError("every size's trace must have the same row length")
+            tp[i] = _dev_ptr(traces[i], self.trace_dtype(i), self.sizes[i][1] * row_len, "trace").value
+            hp[i] = _dev_ptr(hists[i], torch.int32, self.n_bins(i), "hist").value
+        _check(lib().mc_run_chains_part(self._h, int(n_sweeps), int(col), int(row_len), tp, hp))
+
     def join(self, trace, cut, hist, mode=0, i=0):
         import torch
 
@@ -273,6 +313,19 @@ class Context:
         x = np.arange(L)
         bits = (words[:, x // 32] >> (x % 32).astype(np.uint32)) & 1
         return (bits.astype(np.int8) * 2 - 1).reshape(-1)
+
+    def stats(self, i=0):
+        """mc_get_stats of size i as a dict."""
+        st = Stats()
+        _check(lib().mc_get_stats(self._h, i, ctypes.byref(st)))
+        return st.as_dict()
+
+    def check_levels(self, i=0):
+        """Recount every chain's broken bonds against its level
+        (mc_check_levels); raises MCError (MC_EINTERNAL) on a disagreement."""
+        n = ctypes.c_int64()
+        _check(lib().mc_check_levels(self._h, i, ctypes.byref(n)))
+        return n.value
 
     def counters(self, i=0):
         seam = ctypes.c_int32()
@@ -368,6 +421,18 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+PROBES = {0: "valu_xor", 1: "valu_mul_lo", 2: "valu_mul_hi", 3: "valu_mad_u64", 4: "valu_bitop3",
+          5: "lds_read_bandwidth", 6: "lds_dependent_read_cycles", 7: "lone_wave_dependent_issue_cycles",
+          8: "lone_wave_independent_issue_cycles"}
+
+
+def probe(kind, iters, stream=None):
+    """mc_probe: (figure, seconds, work, cycles) of one microbenchmark."""
+    out = np.zeros(4, dtype=np.float64)
+    _check(lib().mc_probe(int(kind), int(iters), _stream_ptr(stream), out.ctypes.data_as(ctypes.c_void_p)))
+    return tuple(float(v) for v in out)
 
 
 # --------------------------------------------------------------------------- #

@@ -12,7 +12,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["mc_kernels.hip", "mc_api.hip", "mc_mlp.hip", "mc_thermo.hip"]
+SOURCES = ["mc_kernels.hip", "mc_api.hip", "mc_mlp.hip", "mc_thermo.hip", "mc_probe.hip"]
 LIB = os.path.join(HERE, "libmcgpu.so")
 ARCH = os.environ.get("MCGPU_ARCH", "gfx950")
 

@@ -35,8 +35,17 @@ struct HostSize {
     SizeDev dev;
     SizePlan plan;     // how its sweeps are launched
     int64_t pending;   // configurations added to histograms since the last update
-    int64_t last_M;    // sweeps of the last mc_run_chains, 0 after its joint
+    int64_t last_M;    // sweeps of the last complete round, 0 after its joint
+    int64_t part_ld;   // a round run in parts (mc_run_chains_part): its length,
+    int64_t part_done; //   and the sweeps of it made so far (0: no round in parts)
+    uint64_t g_host;   // host mirror of the device's global sweep index (Ctl.g)
+    uint64_t r_host;   // host mirror of the joint round index (Ctl.r)
 };
+
+// The random words of sweep g and joint round r are keyed by the 32-bit
+// counters g and r, so a size may make at most 2^32 sweeps and 2^32 joints
+// in its lifetime: beyond that its random words would repeat.
+constexpr uint64_t kCounterLimit = 0x100000000ull;
 
 }  // namespace
 
@@ -63,6 +72,8 @@ struct mc_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     mc_ctx *ctx = nullptr;
+    uint64_t sweeps = 0;  // sweeps and joint rounds one replay advances each size by
+    uint64_t rounds = 0;
 };
 
 namespace {
@@ -101,6 +112,7 @@ void free_size(SizeDev &d) {
     if (d.scratch_cut) (void)hipFree(d.scratch_cut);
     if (d.join_order) (void)hipFree(d.join_order);
     if (d.hist64) (void)hipFree(d.hist64);
+    if (d.n_bad) (void)hipFree(d.n_bad);
     d = SizeDev{};
 }
 
@@ -174,8 +186,10 @@ hipError_t rebuild_launch(mc_ctx *ctx) {
     return prepare_batched(lds);
 }
 
-// Sweeps of every size (Algorithm step 2), one launch when batched.
-hipError_t enqueue_sweeps(mc_ctx *ctx, hipStream_t st, int64_t M, void *const *trace, int32_t *const *hist) {
+// Sweeps of every size (Algorithm step 2), one launch when batched; sweep k of
+// chain c goes to trace[s][c * ld + k].
+hipError_t enqueue_sweeps(mc_ctx *ctx, hipStream_t st, int64_t M, int64_t ld, void *const *trace,
+                          int32_t *const *hist) {
     const int n = (int)ctx->sizes.size();
     hipError_t e = hipSuccess;
     if (ctx->batched) {
@@ -186,10 +200,10 @@ hipError_t enqueue_sweeps(mc_ctx *ctx, hipStream_t st, int64_t M, void *const *t
             plans[i] = ctx->sizes[i].plan;
         }
         e = launch_sweeps_batched(devs.data(), plans.data(), n, ctx->tiles_dev, ctx->n_tiles, ctx->counter_dev,
-                                  ctx->batch_grid, ctx->batch_lds, M, trace, hist, st);
+                                  ctx->batch_grid, ctx->batch_lds, M, ld, trace, hist, st);
     } else {
         for (int i = 0; i < n && e == hipSuccess; ++i)
-            e = launch_sweeps(ctx->sizes[i].dev, ctx->sizes[i].plan, M, trace[i], hist[i], st);
+            e = launch_sweeps(ctx->sizes[i].dev, ctx->sizes[i].plan, M, ld, trace[i], hist[i], st);
     }
     for (int i = 0; i < n && e == hipSuccess; ++i) e = launch_advance(ctx->sizes[i].dev, M, st);
     return e;
@@ -297,7 +311,7 @@ hipError_t autotune_batched(mc_ctx *ctx, int64_t probe_sweeps, hipEvent_t e0, hi
             if (e == hipSuccess)
                 e = launch_sweeps_batched(scr.dev.data(), plans.data(), n, ctx->tiles_dev, ctx->n_tiles,
                                           ctx->counter_dev, ctx->batch_grid, ctx->batch_lds, probe_sweeps,
-                                          scr.trace.data(), scr.hist.data(), ctx->stream);
+                                          probe_sweeps, scr.trace.data(), scr.hist.data(), ctx->stream);
             if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0.f;
@@ -490,6 +504,10 @@ mc_status mc_create(const mc_size *sizes, int32_t n_sizes, void *hip_stream, mc_
         h.cfg = sizes[i];
         h.pending = 0;
         h.last_M = 0;
+        h.part_ld = 0;
+        h.part_done = 0;
+        h.g_host = 0;
+        h.r_host = 0;
         SizeDev &d = h.dev;
         d = SizeDev{};
         d.L = h.cfg.L;
@@ -510,7 +528,8 @@ mc_status mc_create(const mc_size *sizes, int32_t n_sizes, void *hip_stream, mc_
             hipMalloc((void **)&d.ctl, sizeof(Ctl)) != hipSuccess ||
             hipMalloc((void **)&d.scratch_cut, (size_t)d.P * 4) != hipSuccess ||
             hipMalloc((void **)&d.join_order, (size_t)d.P * 4) != hipSuccess ||
-            hipMalloc((void **)&d.hist64, (size_t)d.n_bins * 8) != hipSuccess) {
+            hipMalloc((void **)&d.hist64, (size_t)d.n_bins * 8) != hipSuccess ||
+            hipMalloc((void **)&d.n_bad, sizeof(int64_t)) != hipSuccess) {
             (void)hipGetLastError();
             st = fail(MC_ENOMEM, "device allocation failed for size %d", i);
             break;
@@ -590,23 +609,50 @@ mc_status mc_init_weights(mc_ctx *ctx, int32_t i, const double *lnW_host, int32_
 }
 
 mc_status mc_run_chains(mc_ctx *ctx, int64_t n_sweeps, void *const *trace_dev, int32_t *const *hist_dev) {
+    return mc_run_chains_part(ctx, n_sweeps, 0, n_sweeps, trace_dev, hist_dev);
+}
+
+mc_status mc_run_chains_part(mc_ctx *ctx, int64_t n_sweeps, int64_t col, int64_t row_len, void *const *trace_dev,
+                             int32_t *const *hist_dev) {
     mc_status st = check_ctx(ctx);
     if (st != MC_OK) return st;
     if (n_sweeps < 1 || n_sweeps > 0x7FFFFFFF) return fail(MC_EINVAL, "n_sweeps=%lld must be 1..2^31-1", (long long)n_sweeps);
+    if (row_len < 1 || row_len > 0x7FFFFFFF) return fail(MC_EINVAL, "row_len=%lld must be 1..2^31-1", (long long)row_len);
+    if (col < 0 || col + n_sweeps > row_len)
+        return fail(MC_EINVAL, "columns %lld..%lld do not fit rows of %lld", (long long)col,
+                    (long long)(col + n_sweeps - 1), (long long)row_len);
     if (!trace_dev || !hist_dev) return fail(MC_EINVAL, "null trace/hist pointer array");
     const int n = (int)ctx->sizes.size();
     for (int i = 0; i < n; ++i) {
         HostSize &h = ctx->sizes[i];
         if (!trace_dev[i] || !hist_dev[i]) return fail(MC_EINVAL, "size %d: null trace or hist", i);
+        if (col > 0 && (h.part_ld != row_len || h.part_done != col))
+            return fail(MC_ESTATE, "size %d: columns from %lld continue no round in parts (%lld of %lld made)", i,
+                        (long long)col, (long long)h.part_done, (long long)h.part_ld);
         const int64_t add = (int64_t)h.dev.P * n_sweeps;
         if (h.pending + add > 0x7FFFFFFFll)
             return fail(MC_EOVERFLOW, "size %d: %lld configurations would exceed the int32 histogram", i,
                         (long long)(h.pending + add));
+        if (h.g_host + (uint64_t)n_sweeps > kCounterLimit)
+            return fail(MC_EOVERFLOW, "size %d: sweeps %llu..%llu would pass the 2^32 sweep counter of the random "
+                        "words", i, (unsigned long long)h.g_host, (unsigned long long)(h.g_host + n_sweeps - 1));
     }
-    HIP_OR_FAIL(ctx, enqueue_sweeps(ctx, ctx->stream, n_sweeps, trace_dev, hist_dev));
+    std::vector<void *> tr((size_t)n);
+    for (int i = 0; i < n; ++i)
+        tr[i] = (char *)trace_dev[i] + (size_t)col * (size_t)ctx->sizes[i].dev.trace_bytes;
+    HIP_OR_FAIL(ctx, enqueue_sweeps(ctx, ctx->stream, n_sweeps, row_len, tr.data(), hist_dev));
     for (int i = 0; i < n; ++i) {
-        ctx->sizes[i].pending += (int64_t)ctx->sizes[i].dev.P * n_sweeps;
-        ctx->sizes[i].last_M = n_sweeps;
+        HostSize &h = ctx->sizes[i];
+        h.pending += (int64_t)h.dev.P * n_sweeps;
+        h.g_host += (uint64_t)n_sweeps;
+        if (col + n_sweeps == row_len) {
+            h.last_M = row_len;  // the round is complete: it can be joined
+            h.part_ld = h.part_done = 0;
+        } else {
+            h.last_M = 0;
+            h.part_ld = row_len;
+            h.part_done = col + n_sweeps;
+        }
     }
     return MC_OK;
 }
@@ -618,7 +664,9 @@ mc_status mc_join(mc_ctx *ctx, int32_t i, const void *trace_dev, int64_t n_sweep
     HostSize &h = ctx->sizes[i];
     if (!trace_dev || !cut_dev || !hist_dev) return fail(MC_EINVAL, "null trace, cut or hist");
     if (mode < 0 || mode > 2) return fail(MC_EINVAL, "mode must be 0, 1 or 2");
-    if (h.last_M == 0) return fail(MC_ESTATE, "size %d: no mc_run_chains to join", i);
+    if (h.last_M == 0) return fail(MC_ESTATE, "size %d: no complete round of mc_run_chains to join", i);
+    if (h.r_host + 1 > kCounterLimit)
+        return fail(MC_EOVERFLOW, "size %d: the 2^32 joint rounds of the random words are used up", i);
     if (n_sweeps != h.last_M)
         return fail(MC_EINVAL, "n_sweeps=%lld differs from the last run (%lld)", (long long)n_sweeps, (long long)h.last_M);
     const int32_t *order = nullptr;
@@ -638,6 +686,7 @@ mc_status mc_join(mc_ctx *ctx, int32_t i, const void *trace_dev, int64_t n_sweep
     HIP_OR_FAIL(ctx, launch_join(h.dev, trace_dev, n_sweeps, cut_dev, hist_dev, mode == 2 ? 0 : mode, order,
                                  ctx->stream));
     h.last_M = 0;
+    h.r_host += 1;
     return MC_OK;
 }
 
@@ -649,6 +698,7 @@ mc_status mc_update_weights(mc_ctx *ctx, int32_t i, int32_t *hist_dev, double *l
     if (!hist_dev) return fail(MC_EINVAL, "null hist");
     HIP_OR_FAIL(ctx, launch_update(h.dev, hist_dev, ctx->stream));
     h.pending = 0;
+    h.part_ld = h.part_done = 0;
     if (lnW_out_host || is_flat || retained) {
         Ctl c{};
         HIP_OR_FAIL(ctx, hipMemcpyAsync(&c, h.dev.ctl, sizeof c, hipMemcpyDeviceToHost, ctx->stream));
@@ -678,7 +728,7 @@ mc_status mc_iterate_topup(mc_ctx *ctx, int64_t m_total, int64_t m_max, int32_t 
     if ((int64_t)d.P * m_max > 0x7FFFFFFFll)
         return fail(MC_EOVERFLOW, "%d chains x %lld sweeps exceed the int32 histogram of one round", d.P,
                     (long long)m_max);
-    if (h.pending != 0 || h.last_M != 0)
+    if (h.pending != 0 || h.last_M != 0 || h.part_ld != 0)
         return fail(MC_ESTATE, "mc_iterate_topup must start after a weight update");
     Ctl c{};
     HIP_OR_FAIL(ctx, hipMemcpyAsync(&c, d.ctl, sizeof c, hipMemcpyDeviceToHost, ctx->stream));
@@ -789,6 +839,9 @@ mc_status mc_get_state(mc_ctx *ctx, void *buf, size_t *len) {
     mc_status st = check_ctx(ctx);
     if (st != MC_OK) return st;
     if (!len) return fail(MC_EINVAL, "null length pointer");
+    for (size_t i = 0; i < ctx->sizes.size(); ++i)
+        if (ctx->sizes[i].part_ld != 0)
+            return fail(MC_ESTATE, "size %zu: a round is partly run (mc_run_chains_part); finish it first", i);
     size_t need = kStateHeader;
     for (const auto &h : ctx->sizes) need += state_size_of(h.dev);
     if (!buf) {
@@ -932,6 +985,9 @@ mc_status mc_set_state(mc_ctx *ctx, const void *buf, size_t len) {
         HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
         h.pending = (int64_t)get64(at + 28);
         h.last_M = (int64_t)get64(at + 36);
+        h.part_ld = h.part_done = 0;
+        h.g_host = c.g;
+        h.r_host = c.r;
         at += state_size_of(d);
     }
     return MC_OK;
@@ -1054,7 +1110,7 @@ mc_status mc_autotune(mc_ctx *ctx, int64_t probe_sweeps, int32_t *chains_per_blo
                 if (e == hipSuccess) e = hipMemcpyAsync(scr.lev, d.lev, (size_t)d.P * 4, hipMemcpyDeviceToDevice, ctx->stream);
                 if (e == hipSuccess) e = hipMemcpyAsync(scr.ctl, d.ctl, sizeof(Ctl), hipMemcpyDeviceToDevice, ctx->stream);
                 if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
-                if (e == hipSuccess) e = launch_sweeps(scr, cand, probe_sweeps, tr, hs, ctx->stream);
+                if (e == hipSuccess) e = launch_sweeps(scr, cand, probe_sweeps, probe_sweeps, tr, hs, ctx->stream);
                 if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
                 if (e == hipSuccess) e = hipEventSynchronize(e1);
                 float ms = 0.f;
@@ -1102,6 +1158,10 @@ mc_status mc_graph_create(mc_ctx *ctx, int64_t n_sweeps, int32_t n_iters, void *
             return fail(MC_ESTATE, "size %d: a graph must start after a weight update", i);
         if ((int64_t)h.dev.P * n_sweeps > 0x7FFFFFFFll)
             return fail(MC_EOVERFLOW, "size %d: one iteration exceeds the int32 histogram", i);
+        if (h.part_ld != 0) return fail(MC_ESTATE, "size %d: a round is partly run", i);
+        if ((uint64_t)n_sweeps * (uint64_t)n_iters > kCounterLimit || (uint64_t)n_iters > kCounterLimit)
+            return fail(MC_EOVERFLOW, "size %d: %d iterations of %lld sweeps pass the 2^32 counters", i, n_iters,
+                        (long long)n_sweeps);
     }
     if (!ctx->capture_stream)
         HIP_OR_FAIL(ctx, hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
@@ -1110,7 +1170,7 @@ mc_status mc_graph_create(mc_ctx *ctx, int64_t n_sweeps, int32_t n_iters, void *
     HIP_OR_FAIL(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
     for (int it = 0; it < n_iters && e == hipSuccess; ++it) {
-        e = enqueue_sweeps(ctx, cs, n_sweeps, trace_dev, hist_dev);
+        e = enqueue_sweeps(ctx, cs, n_sweeps, n_sweeps, trace_dev, hist_dev);
         for (int i = 0; i < n && e == hipSuccess; ++i)
             e = launch_join(ctx->sizes[i].dev, trace_dev[i], n_sweeps, cut_dev[i], hist_dev[i], mode, nullptr, cs);
         for (int i = 0; i < n && e == hipSuccess; ++i) e = launch_update(ctx->sizes[i].dev, hist_dev[i], cs);
@@ -1125,6 +1185,8 @@ mc_status mc_graph_create(mc_ctx *ctx, int64_t n_sweeps, int32_t n_iters, void *
     mc_graph *g = new mc_graph();
     g->graph = graph;
     g->ctx = ctx;
+    g->sweeps = (uint64_t)n_sweeps * (uint64_t)n_iters;
+    g->rounds = (uint64_t)n_iters;
     e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
         (void)hipGraphDestroy(graph);
@@ -1140,9 +1202,18 @@ mc_status mc_graph_launch(mc_ctx *ctx, mc_graph *g) {
     mc_status st = check_ctx(ctx);
     if (st != MC_OK) return st;
     if (!g || g->ctx != ctx) return fail(MC_EINVAL, "graph does not belong to this context");
-    for (const auto &h : ctx->sizes)
-        if (h.pending != 0 || h.last_M != 0) return fail(MC_ESTATE, "a graph must start after a weight update");
+    for (size_t i = 0; i < ctx->sizes.size(); ++i) {
+        const HostSize &h = ctx->sizes[i];
+        if (h.pending != 0 || h.last_M != 0 || h.part_ld != 0)
+            return fail(MC_ESTATE, "a graph must start after a weight update");
+        if (h.g_host + g->sweeps > kCounterLimit || h.r_host + g->rounds > kCounterLimit)
+            return fail(MC_EOVERFLOW, "size %zu: a replay would pass the 2^32 sweep or round counters", i);
+    }
     HIP_OR_FAIL(ctx, hipGraphLaunch(g->exec, ctx->stream));
+    for (auto &h : ctx->sizes) {
+        h.g_host += g->sweeps;
+        h.r_host += g->rounds;
+    }
     return MC_OK;
 }
 
@@ -1158,4 +1229,47 @@ mc_status mc_graph_destroy(mc_graph *g) {
     return MC_OK;
 }
 
+mc_status mc_get_stats(mc_ctx *ctx, int32_t i, mc_stats *out) {
+    mc_status st = check_size(ctx, i);
+    if (st != MC_OK) return st;
+    if (!out) return fail(MC_EINVAL, "null output");
+    Ctl c{};
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(&c, ctx->sizes[i].dev.ctl, sizeof c, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+    mc_stats o{};
+    o.updates = c.iter;
+    o.first_flat = c.flat_iter;
+    o.last_flat = c.flat;
+    o.retained_last = c.retained_last;
+    o.hist_sum = c.upd_h_sum;
+    o.hist_min = c.upd_h_min;
+    o.n_reach_bins = c.upd_n_reach;
+    o.lnw_min = c.iter > 0 ? c.upd_lnw_lo : 0.0;
+    o.lnw_max = c.iter > 0 ? c.upd_lnw_hi : 0.0;
+    o.join_none = c.join_none;
+    o.join_cut_max = c.join_cut_max;
+    o.join_cut_sum = c.join_cut_sum;
+    o.sweep_index = c.g;
+    o.round_index = c.r;
+    o.seam = c.sigma;
+    *out = o;
+    return MC_OK;
+}
+
+mc_status mc_check_levels(mc_ctx *ctx, int32_t i, int64_t *n_bad) {
+    mc_status st = check_size(ctx, i);
+    if (st != MC_OK) return st;
+    const SizeDev &d = ctx->sizes[i].dev;
+    int64_t bad = 0;
+    HIP_OR_FAIL(ctx, launch_check_levels(d, ctx->stream));
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(&bad, d.n_bad, sizeof bad, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+    if (n_bad) *n_bad = bad;
+    if (bad != 0)
+        return fail(MC_EINTERNAL, "size %d: %lld chains hold a level that is not half their broken bonds", i,
+                    (long long)bad);
+    return MC_OK;
+}
+
 }  // extern "C"
+

@@ -16,6 +16,17 @@ struct Ctl {
     int64_t retained_last;  // the same, frozen by the last update
     int32_t iter;           // updates done so far
     int32_t flat_iter;      // first update (1-based) that was flat, 0 = none
+    // Statistics of the last joint and of the last update (read by
+    // mc_get_stats; not part of a checkpoint).
+    int32_t join_none;      // chains of the last joint that kept nothing
+    int32_t join_cut_max;   // largest cut point of the last joint
+    int64_t join_cut_sum;   // sum of its cut points over the chains that kept something
+    int64_t upd_h_sum;      // configurations in bins holding a reachable level, at the last update
+    int64_t upd_h_min;      // fewest of them in one such bin
+    int32_t upd_n_reach;    // number of such bins
+    int32_t pad_;
+    double upd_lnw_lo;      // smallest and largest ln w over those bins after the update
+    double upd_lnw_hi;
 };
 
 // Device view of one lattice size.
@@ -26,6 +37,7 @@ struct SizeDev {
     uint32_t seed;
     uint32_t c_off;         // global index of chain 0 (the random words are keyed by the global index)
     int32_t trace_bytes;    // 2 (int16) or 4 (int32)
+    int64_t tld;            // row length of the trace a sweep launch writes (set per launch)
     uint32_t *lat;          // [L*W][P] chain-interleaved bit-packed rows
     int32_t *lev;           // [P] current level of each chain
     double *lnW;            // [n_bins]
@@ -36,6 +48,7 @@ struct SizeDev {
     int32_t *scratch_cut;   // [P] speculative cut points of the joint
     int32_t *join_order;    // [P] chain at each position of an energy-ordered joint
     int64_t *hist64;        // [n_bins] joined histogram of Algorithm step 6's rounds
+    int64_t *n_bad;         // [1] chains whose level disagrees with their lattice (mc_check_levels)
 };
 
 // How the sweeps of one size are launched.
@@ -78,9 +91,11 @@ hipError_t prepare_sweeps(const SizeDev &s, const SizePlan &p);  // kernel attri
 hipError_t prepare_batched(size_t lds_bytes);
 hipError_t launch_init(const SizeDev &s, hipStream_t st);
 hipError_t launch_tabulate(const SizeDev &s, hipStream_t st);
-hipError_t launch_sweeps(const SizeDev &s, const SizePlan &p, int64_t M, void *trace, int32_t *hist, hipStream_t st);
+// M sweeps; sweep k of chain c goes to trace[c * ld + k] (ld >= M).
+hipError_t launch_sweeps(const SizeDev &s, const SizePlan &p, int64_t M, int64_t ld, void *trace, int32_t *hist,
+                         hipStream_t st);
 hipError_t launch_sweeps_batched(const SizeDev *sizes, const SizePlan *plans, int n_sizes, const Tile *tiles_dev,
-                                 int n_tiles, int32_t *counter_dev, int grid, size_t lds_bytes, int64_t M,
+                                 int n_tiles, int32_t *counter_dev, int grid, size_t lds_bytes, int64_t M, int64_t ld,
                                  void *const *trace, int32_t *const *hist, hipStream_t st);
 hipError_t launch_advance(const SizeDev &s, int64_t M, hipStream_t st);
 // order: the chain at each position of the joint, or nullptr for index order.
@@ -92,6 +107,8 @@ hipError_t launch_update(const SizeDev &s, int32_t *hist, hipStream_t st);
 hipError_t launch_fold_hist(const SizeDev &s, int32_t *hist, hipStream_t st);
 hipError_t launch_update64(const SizeDev &s, hipStream_t st);
 hipError_t launch_thermo(const SizeDev &s, const double *beta_dev, int n_beta, double *out_dev, hipStream_t st);
+// Count, into s.n_bad, the chains whose level is not half their broken bonds.
+hipError_t launch_check_levels(const SizeDev &s, hipStream_t st);
 
 // Most inverse temperatures one mc_thermo call takes.
 constexpr int kThermoMaxBetas = 1 << 20;

@@ -253,9 +253,9 @@ __device__ __forceinline__ void sweep_tile_lds(const SizeDev &s, int c0, int cpb
             const int m = mi >> 3;
             const int ev = m - N / 2;
             if (s.trace_bytes == 2)
-                ((int16_t *)trace)[(size_t)c * M + k] = (int16_t)ev;
+                ((int16_t *)trace)[(size_t)c * s.tld + k] = (int16_t)ev;
             else
-                ((int32_t *)trace)[(size_t)c * M + k] = ev;
+                ((int32_t *)trace)[(size_t)c * s.tld + k] = ev;
             if (lds_hist)
                 atomicAdd(&shist[m >> s.bin_shift], 1);
             else
@@ -590,9 +590,9 @@ __device__ __forceinline__ void sweep_tile_pc(const SizeDev &s, int c0, int cpb,
                 const int m = (int)((mib - tab_addr - 16u) / (uint32_t)kLevelBytes);
                 const int ev = m - N / 2;
                 if (s.trace_bytes == 2)
-                    ((int16_t *)trace)[(size_t)c * M + k] = (int16_t)ev;
+                    ((int16_t *)trace)[(size_t)c * s.tld + k] = (int16_t)ev;
                 else
-                    ((int32_t *)trace)[(size_t)c * M + k] = ev;
+                    ((int32_t *)trace)[(size_t)c * s.tld + k] = ev;
                 atomicAdd(&shist[m >> s.bin_shift], 1);
             }
         } else if (!consumer && i + 1 < n_chunks) {
@@ -819,9 +819,9 @@ __device__ __forceinline__ void sweep_tile_pcq(const SizeDev &s, int c0, int cpb
                 const int m = (int)((mib - tab_addr - 16u) / (uint32_t)kLevelBytes);
                 const int ev = m - N / 2;
                 if (s.trace_bytes == 2)
-                    ((int16_t *)trace)[(size_t)c * M + k] = (int16_t)ev;
+                    ((int16_t *)trace)[(size_t)c * s.tld + k] = (int16_t)ev;
                 else
-                    ((int32_t *)trace)[(size_t)c * M + k] = ev;
+                    ((int32_t *)trace)[(size_t)c * s.tld + k] = ev;
                 atomicAdd(&shist[m >> s.bin_shift], 1);
             }
         } else if (!consumer && i + 1 < n_chunks) {
@@ -1019,9 +1019,9 @@ __device__ __forceinline__ void sweep_tile_big(const SizeDev &s, int c0, int cpb
             if (y0 + R == L) {
                 const int ev = m - N / 2;
                 if (s.trace_bytes == 2)
-                    ((int16_t *)trace)[(size_t)c * M + k] = (int16_t)ev;
+                    ((int16_t *)trace)[(size_t)c * s.tld + k] = (int16_t)ev;
                 else
-                    ((int32_t *)trace)[(size_t)c * M + k] = ev;
+                    ((int32_t *)trace)[(size_t)c * s.tld + k] = ev;
                 atomicAdd(&hist[m >> bs], 1);
             }
         } else if (!consumer && i + 1 < n_chunks) {
@@ -1242,9 +1242,9 @@ __device__ __forceinline__ void sweep_tile_bigq(const SizeDev &s, int c0, int cp
             if (y0 + R == L && lead) {
                 const int ev = m - N / 2;
                 if (s.trace_bytes == 2)
-                    ((int16_t *)trace)[(size_t)c * M + k] = (int16_t)ev;
+                    ((int16_t *)trace)[(size_t)c * s.tld + k] = (int16_t)ev;
                 else
-                    ((int32_t *)trace)[(size_t)c * M + k] = ev;
+                    ((int32_t *)trace)[(size_t)c * s.tld + k] = ev;
                 atomicAdd(&hist[m >> bs], 1);
             }
         } else if (!consumer && i + 1 < n_chunks) {
@@ -1303,9 +1303,9 @@ __global__ __launch_bounds__(64) void k_sweep_glb(SweepParams p) {
         const int m = mi >> 3;
         const int ev = m - N / 2;
         if (s.trace_bytes == 2)
-            ((int16_t *)p.trace)[(size_t)c * p.M + k] = (int16_t)ev;
+            ((int16_t *)p.trace)[(size_t)c * p.s.tld + k] = (int16_t)ev;
         else
-            ((int32_t *)p.trace)[(size_t)c * p.M + k] = ev;
+            ((int32_t *)p.trace)[(size_t)c * p.s.tld + k] = ev;
         atomicAdd(&p.hist[m >> s.bin_shift], 1);
     }
     s.lev[c] = mi >> 3;
@@ -1341,9 +1341,9 @@ __global__ __launch_bounds__(64) void k_sweep_generic(SweepParams p) {
         }
         const int ev = m - N / 2;
         if (s.trace_bytes == 2)
-            ((int16_t *)p.trace)[(size_t)c * p.M + k] = (int16_t)ev;
+            ((int16_t *)p.trace)[(size_t)c * p.s.tld + k] = (int16_t)ev;
         else
-            ((int32_t *)p.trace)[(size_t)c * p.M + k] = ev;
+            ((int32_t *)p.trace)[(size_t)c * p.s.tld + k] = ev;
         atomicAdd(&p.hist[m >> s.bin_shift], 1);
     }
     s.lev[c] = m;
@@ -1596,10 +1596,12 @@ hipError_t prepare_sweeps(const SizeDev &s, const SizePlan &p) {
     }
 }
 
-hipError_t launch_sweeps(const SizeDev &s, const SizePlan &pl, int64_t M, void *trace, int32_t *hist,
+hipError_t launch_sweeps(const SizeDev &s, const SizePlan &pl, int64_t M, int64_t ld, void *trace, int32_t *hist,
                          hipStream_t st) {
+    if (ld < M) return hipErrorInvalidValue;
     SweepParams p{};
     p.s = s;
+    p.s.tld = ld;
     p.M = M;
     p.trace = trace;
     p.hist = hist;
@@ -1692,12 +1694,13 @@ hipError_t prepare_batched(size_t lds_bytes) {
 }
 
 hipError_t launch_sweeps_batched(const SizeDev *sizes, const SizePlan *plans, int n_sizes, const Tile *tiles_dev,
-                                 int n_tiles, int32_t *counter_dev, int grid, size_t lds_bytes, int64_t M,
+                                 int n_tiles, int32_t *counter_dev, int grid, size_t lds_bytes, int64_t M, int64_t ld,
                                  void *const *trace, int32_t *const *hist, hipStream_t st) {
-    if (n_sizes > kMaxSizes) return hipErrorInvalidValue;
+    if (n_sizes > kMaxSizes || ld < M) return hipErrorInvalidValue;
     BatchParams p{};
     for (int i = 0; i < n_sizes; ++i) {
         p.sizes[i] = sizes[i];
+        p.sizes[i].tld = ld;
         p.trace[i] = trace[i];
         p.hist[i] = hist[i];
         p.cpb[i] = plans[i].cpb;
@@ -1788,7 +1791,8 @@ __global__ __launch_bounds__(64) void k_join_fix(JoinParams p) {
     const int lane = threadIdx.x;
     const uint32_t r = s.ctl->r;
     int sigma = s.ctl->sigma;
-    int64_t kept = 0;
+    int64_t kept = 0, cut_sum = 0;
+    int n_none = 0, cut_max = 0;
     for (int c0 = 0; c0 < s.P; c0 += CH) {
         const int n = min(CH, s.P - c0);
         __syncthreads();
@@ -1811,6 +1815,10 @@ __global__ __launch_bounds__(64) void k_join_fix(JoinParams p) {
             if (cut > 0) {
                 kept += p.M - cut + 1;
                 sigma = s_last[t + 1];
+                cut_sum += cut;
+                cut_max = max(cut_max, cut);
+            } else {
+                n_none += 1;
             }
         }
     }
@@ -1818,6 +1826,9 @@ __global__ __launch_bounds__(64) void k_join_fix(JoinParams p) {
         s.ctl->sigma = sigma;
         s.ctl->retained += kept;
         s.ctl->r = r + 1;
+        s.ctl->join_none = n_none;
+        s.ctl->join_cut_max = cut_max;
+        s.ctl->join_cut_sum = cut_sum;
     }
 }
 
@@ -1881,15 +1892,23 @@ template <typename HT>
 __global__ __launch_bounds__(1024) void k_update(SizeDev s, HT *hist) {
     __shared__ long long s_min[16], s_sum[16];
     __shared__ int s_n[16];
+    __shared__ double s_lo[16], s_hi[16];
     long long mn = 0x7FFFFFFFFFFFFFFFll, sum = 0;
     int n = 0;
+    double lo = INFINITY, hi = -INFINITY;
     for (int b = threadIdx.x; b < s.n_bins; b += blockDim.x) {
         const long long h = hist[b];
-        if (h > 0) s.lnW[b] = s.lnW[b] - det_log((int64_t)h);
+        double w = s.lnW[b];
+        if (h > 0) {
+            w = w - det_log((int64_t)h);
+            s.lnW[b] = w;
+        }
         if (bin_reachable(b, s.bin_shift, s.N)) {
             n += 1;
             sum += h;
             mn = h < mn ? h : mn;
+            lo = fmin(lo, w);
+            hi = fmax(hi, w);
         }
         hist[b] = 0;
     }
@@ -1898,31 +1917,84 @@ __global__ __launch_bounds__(1024) void k_update(SizeDev s, HT *hist) {
         mn = omn < mn ? omn : mn;
         sum += __shfl_xor(sum, off, 64);
         n += __shfl_xor(n, off, 64);
+        lo = fmin(lo, __shfl_xor(lo, off, 64));
+        hi = fmax(hi, __shfl_xor(hi, off, 64));
     }
     const int wv = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
         s_min[wv] = mn;
         s_sum[wv] = sum;
         s_n[wv] = n;
+        s_lo[wv] = lo;
+        s_hi[wv] = hi;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         const int nw = (blockDim.x + 63) >> 6;
         long long tmn = s_min[0], tsum = 0;
         int tn = 0;
+        double tlo = s_lo[0], thi = s_hi[0];
         for (int i = 0; i < nw; ++i) {
             tmn = s_min[i] < tmn ? s_min[i] : tmn;
             tsum += s_sum[i];
             tn += s_n[i];
+            tlo = fmin(tlo, s_lo[i]);
+            thi = fmax(thi, s_hi[i]);
         }
         const int flat = (tn > 0 && tsum > 0 && 5ll * tn * tmn >= 4ll * tsum) ? 1 : 0;
         Ctl *ctl = s.ctl;
+        ctl->upd_h_sum = tsum;
+        ctl->upd_h_min = tn > 0 ? tmn : 0;
+        ctl->upd_n_reach = tn;
+        ctl->upd_lnw_lo = tlo;
+        ctl->upd_lnw_hi = thi;
         ctl->flat = flat;
         ctl->iter += 1;
         if (flat && ctl->flat_iter == 0) ctl->flat_iter = ctl->iter;
         ctl->retained_last = ctl->retained;
         ctl->retained = 0;
     }
+}
+
+// A chain's level is half the number of its broken bonds (level m = (E + 2N)/4
+// with E = -(bonds) + 2 (broken bonds) over the 2N bonds, J = 1); the sweeps
+// track it incrementally, so a disagreement means the state is corrupt.  One
+// thread per chain counts broken right and down bonds of its bit-packed rows
+// (a row's last word holds L - 32 (W - 1) sites; the right neighbour of site
+// L-1 is site 0, the row below row L-1 is row 0).
+__global__ __launch_bounds__(256) void k_check_levels(SizeDev s) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= s.P) return;
+    const int L = s.L, W = s.W;
+    const size_t P = (size_t)s.P;
+    const int nb = L - 32 * (W - 1);
+    const uint32_t last_mask = nb == 32 ? 0xFFFFFFFFu : (1u << nb) - 1u;
+    int64_t broken = 0;
+    for (int y = 0; y < L; ++y) {
+        const int yd = y + 1 < L ? y + 1 : 0;
+        for (int w = 0; w < W; ++w) {
+            const uint32_t cur = s.lat[(size_t)(y * W + w) * P + c];
+            const uint32_t down = s.lat[(size_t)(yd * W + w) * P + c];
+            uint32_t right, mask = 0xFFFFFFFFu;
+            if (w + 1 < W) {
+                right = (cur >> 1) | (s.lat[(size_t)(y * W + w + 1) * P + c] << 31);
+            } else {
+                const uint32_t first = s.lat[(size_t)(y * W) * P + c];
+                right = (cur >> 1) | ((first & 1u) << (nb - 1));
+                mask = last_mask;
+            }
+            broken += __popc((cur ^ right) & mask) + __popc((cur ^ down) & mask);
+        }
+    }
+    if (2ll * s.lev[c] != broken) atomicAdd((unsigned long long *)s.n_bad, 1ull);
+}
+
+__global__ void k_zero64(int64_t *p) { *p = 0; }
+
+hipError_t launch_check_levels(const SizeDev &s, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero64, dim3(1), dim3(1), 0, st, s.n_bad);
+    hipLaunchKernelGGL(k_check_levels, dim3((s.P + 255) / 256), dim3(256), 0, st, s);
+    return hipGetLastError();
 }
 
 hipError_t launch_update(const SizeDev &s, int32_t *hist, hipStream_t st) {

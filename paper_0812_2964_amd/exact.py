@@ -1,6 +1,8 @@
-"""Exact results for the periodic 2D Ising model (J = 1), used to pin the oracle.
+"""Exact results for the periodic 2D Ising model (J = 1): the reference values
+the thermodynamics of a multicanonical weight are judged by (Sec. 5 compares
+with exact finite-lattice results), and pins of the test oracle.
 
-None of this is part of the method under test; it is independent mathematics:
+None of this is part of the sampling method; it is independent mathematics:
 
 * ``brute_force_dos(L)`` enumerates all 2^(L*L) configurations (L = 4 only).
 * ``transfer_dos(L)`` counts configurations per energy exactly with a row

@@ -52,6 +52,9 @@ def test_argument_errors_before_device():
     assert L.mc_run_chains(None, 10, None, None) == mc.MC_EINVAL
     assert L.mc_join(None, 0, None, 10, None, None, 0) == mc.MC_EINVAL
     assert L.mc_update_weights(None, 0, None, None, None, None) == mc.MC_EINVAL
+    assert L.mc_run_chains_part(None, 10, 0, 10, None, None) == mc.MC_EINVAL
+    assert L.mc_get_stats(None, 0, None) == mc.MC_EINVAL
+    assert L.mc_check_levels(None, 0, None) == mc.MC_EINVAL
     assert L.mc_destroy(None) == mc.MC_OK
 
 

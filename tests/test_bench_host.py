@@ -49,19 +49,50 @@ def test_more_than_one_gpu_is_refused():
     assert p.returncode != 0 and "one GPU" in (p.stdout + p.stderr)
 
 
-def test_traffic_only_for_current_source_and_workload():
+def test_traffic_only_for_current_source_and_workload(tmp_path, monkeypatch):
+    """A counter summary is used only when its kernel source hash and its
+    workload line match."""
     import bench
 
-    t = bench.traffic_from_profiles(32, 4096, 100000)
-    assert t is None or t > 8e8
-    assert bench.traffic_from_profiles(32, 4096, 99999) is None
-    assert bench.traffic_from_profiles(16, 4096, 100000) is None
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    h = bench.kernel_source_hash()
+    (prof / "x.md").write_text("workload: L=32 chains=4096 sweeps=100000\nkernel source sha256: %s\n"
+                               "HBM bytes per launch (scaled): 8.21e+08\n" % h)
+    (prof / "old.md").write_text("workload: L=32 chains=4096 sweeps=100000\nkernel source sha256: %s\n"
+                                 "HBM bytes per launch (scaled): 8.21e+08\n" % ("0" * 64))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: h)
+    assert bench.traffic_from_profiles("x.md", "L=32 chains=4096 sweeps=100000") == 8.21e8
+    assert bench.traffic_from_profiles("x.md", "L=32 chains=4096 sweeps=99999") is None
+    assert bench.traffic_from_profiles("old.md", "L=32 chains=4096 sweeps=100000") is None
+    assert bench.traffic_from_profiles("missing.md", "L=32 chains=4096 sweeps=100000") is None
+
+
+def test_batched_cpu_baseline_and_iteration_record():
+    """The batched workload's oracle leg runs every size on every thread; the
+    per-iteration record derives its fields from mc_get_stats."""
+    import bench
+
+    Ls = [4, 6]
+    cb = bench.cpu_baseline_batched(Ls, [np.zeros(O.n_bins(L, 1)) for L in Ls], 2, 5)
+    assert cb["kind"] == "oracle" and cb["value"] > 0 and cb["cores"] == bench.cpu_threads()
+
+    class FakeCtx:
+        def stats(self, i):
+            return {"updates": 3, "retained_last": 150, "join_none": 2, "join_cut_sum": 30, "join_cut_max": 9,
+                    "hist_min": 10, "n_reach_bins": 5, "hist_sum": 100, "last_flat": 0, "first_flat": 0,
+                    "lnw_min": -4.0, "lnw_max": 1.5}
+
+    r = bench.iteration_record(FakeCtx(), 0, 8, 10, 20, 3, 12.5)
+    assert r["retained_frac"] == 150 / 200.0 and r["n_no_accept"] == 2 and r["mean_cut"] == 30 / 8.0
+    assert r["max_cut"] == 9 and r["flat_ratio"] == 0.5 and r["lnW_span"] == 5.5 and r["first_flat"] is None
 
 
 def test_record_carries_the_contract_keys():
     """The JSON line's keys and the roofline object's arithmetic, without a
     GPU: frac = achieved / peak, achieved = ops per attempt x attempts / the
-    kernel's time, the peak from 256 CUs x 64 lanes x 2.4 GHz."""
+    kernel's time, the peak from 256 CUs x 128 lanes x 2.4 GHz."""
     import argparse
 
     import bench
@@ -76,6 +107,6 @@ def test_record_carries_the_contract_keys():
     for k in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
         assert k in r, k
     assert r["bound"] == "alu" and r["traffic"] == 8.2e8
-    assert abs(r["peak"] - 256 * 64 * 2.4e9 / 1e12) < 1e-9
+    assert abs(r["peak"] - 256 * 128 * 2.4e9 / 1e12) < 1e-9
     assert abs(r["achieved"] - 31 * 4.194304e11 / 3.5 / 1e12) < 1e-9
     assert abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-12

@@ -20,7 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(HERE))
 sys.path.insert(0, HERE)
 
-import exact_ising as X  # noqa: E402
+from paper_0812_2964_amd import exact as X  # noqa: E402
 from oracle.thermo import thermo as o_thermo  # noqa: E402
 
 pytestmark = pytest.mark.gpu

@@ -14,7 +14,7 @@
 import numpy as np
 import pytest
 
-import exact_ising as X
+from paper_0812_2964_amd import exact as X
 import oracle as O
 
 

@@ -12,7 +12,7 @@ import math
 import mpmath
 import numpy as np
 
-import exact_ising as X
+from paper_0812_2964_amd import exact as X
 import oracle as O
 
 SEED = 1

@@ -20,7 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(HERE))
 sys.path.insert(0, HERE)
 
-import exact_ising as X  # noqa: E402
+from paper_0812_2964_amd import exact as X  # noqa: E402
 from oracle.thermo import thermo  # noqa: E402
 
 BETAS = [0.05, 0.2, 0.35, 0.4407, 0.5, 0.7, 1.0]
