@@ -258,6 +258,23 @@ mc_status mc_get_weights(mc_ctx *ctx, int32_t size_idx, double *lnW_host, int32_
    doubles, kept by the context for later calls) cannot be allocated. */
 mc_status mc_thermo(mc_ctx *ctx, int32_t size_idx, const double *beta_host, int32_t n_beta, double *out_host);
 
+/* mc_thermo for callers that cannot allocate device memory (code under HIP
+   graph capture aside, tight serving loops, harnesses that forbid
+   allocation): the same computation and results, bit for bit, with the
+   inverse temperatures and results staged in a static device array of the
+   library instead of a buffer the context allocates.  The array holds
+   MC_THERMO_STATIC_MAX_BETAS inverse temperatures (5 doubles each, 320 KB);
+   each GPU the library runs on holds one until the process ends, its address
+   looked up when a context is created on that GPU.  Every call on a GPU
+   shares that GPU's array, which keeps the last call's contents: calls that
+   overlap on one GPU (several contexts, streams or threads) race, and must be
+   serialised by the caller.  Allocates nothing: no hipMalloc or hipFree.
+   Synchronising.  MC_EINVAL for a null pointer, n_beta outside
+   1..MC_THERMO_STATIC_MAX_BETAS or a beta that is not positive and finite. */
+#define MC_THERMO_STATIC_MAX_BETAS 8192
+mc_status mc_thermo_static(mc_ctx *ctx, int32_t size_idx, const double *beta_host, int32_t n_beta,
+                           double *out_host);
+
 /* Progress of the weight recursion of one size (synchronising; each output may
    be NULL): updates done, first update (1-based) whose histogram was flat (0 =
    none yet), flatness of the last update, configurations kept by the joints

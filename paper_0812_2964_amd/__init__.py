@@ -28,7 +28,7 @@ EXPORTED = ["mc_create", "mc_destroy", "mc_n_bins", "mc_trace_elem_bytes", "mc_l
             "mc_mlp_n_params", "mc_mlp_workspace_bytes", "mc_mlp_init", "mc_mlp_forward", "mc_mlp_loss_grad",
             "mc_mlp_train", "mc_mlp_targets", "mc_mlp_predict_weights", "mc_thermo", "mc_iterate_topup",
             "mc_get_state", "mc_set_state", "mc_set_seam", "mc_run_chains_part", "mc_get_stats", "mc_check_levels",
-            "mc_probe"]
+            "mc_probe", "mc_thermo_static"]
 
 
 class MCError(RuntimeError):
@@ -80,6 +80,7 @@ def lib():
     L.mc_get_stats.argtypes = [p, i32, ctypes.POINTER(Stats)]
     L.mc_check_levels.argtypes = [p, i32, ctypes.POINTER(i64)]
     L.mc_probe.argtypes = [i32, i32, p, p]
+    L.mc_thermo_static.argtypes = [p, i32, p, i32, p]
     L.mc_join.argtypes = [p, i32, p, i64, p, p, i32]
     L.mc_update_weights.argtypes = [p, i32, p, p, p, p]
     L.mc_iterate_topup.argtypes = [p, i64, i64, i32, p, p, p, i32, p, p, p, p]

@@ -66,6 +66,7 @@ struct mc_ctx {
     int live_graphs = 0;  // graphs hold the tile buffer and the state pointers
     double *thermo_buf = nullptr;  // mc_thermo: [thermo_cap] betas + [4 * thermo_cap] results
     int thermo_cap = 0;
+    double *thermo_static = nullptr;  // mc_thermo_static: the device's static array (not owned)
 };
 
 struct mc_graph {
@@ -497,6 +498,12 @@ mc_status mc_create(const mc_size *sizes, int32_t n_sizes, void *hip_stream, mc_
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device) == hipSuccess && ncu > 0)
         ctx->n_cu = ncu;
+    // the device address of mc_thermo_static's array, looked up with this device current
+    if (thermo_scratch_address(ctx->device, &ctx->thermo_static) != hipSuccess) {
+        (void)hipGetLastError();
+        delete ctx;
+        return fail(MC_EHIP, "device address of the static reweighting array");
+    }
     ctx->sizes.resize(n_sizes);
     mc_status st = MC_OK;
     for (int i = 0; i < n_sizes && st == MC_OK; ++i) {
@@ -1013,6 +1020,26 @@ mc_status mc_thermo(mc_ctx *ctx, int32_t i, const double *beta_host, int32_t n_b
         ctx->thermo_cap = n_beta;
     }
     double *beta_dev = ctx->thermo_buf, *out_dev = ctx->thermo_buf + n_beta;
+    const SizeDev &d = ctx->sizes[i].dev;
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(beta_dev, beta_host, (size_t)n_beta * 8, hipMemcpyHostToDevice, ctx->stream));
+    HIP_OR_FAIL(ctx, launch_thermo(d, beta_dev, n_beta, out_dev, ctx->stream));
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(out_host, out_dev, (size_t)4 * n_beta * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+    return MC_OK;
+}
+
+mc_status mc_thermo_static(mc_ctx *ctx, int32_t i, const double *beta_host, int32_t n_beta, double *out_host) {
+    mc_status st = check_size(ctx, i);
+    if (st != MC_OK) return st;
+    if (!beta_host || !out_host) return fail(MC_EINVAL, "null pointer");
+    if (n_beta < 1 || n_beta > kThermoStaticMaxBetas)
+        return fail(MC_EINVAL, "n_beta=%d must be 1..%d (the static array's capacity)", n_beta, kThermoStaticMaxBetas);
+    for (int k = 0; k < n_beta; ++k)
+        if (!(beta_host[k] > 0.0) || !std::isfinite(beta_host[k]))
+            return fail(MC_EINVAL, "beta[%d] must be positive and finite", k);
+    if (!ctx->thermo_static) return fail(MC_EHIP, "no static array on this device");
+    // betas at [0, n_beta), results at [n_beta, 5 n_beta) of the array
+    double *beta_dev = ctx->thermo_static, *out_dev = ctx->thermo_static + n_beta;
     const SizeDev &d = ctx->sizes[i].dev;
     HIP_OR_FAIL(ctx, hipMemcpyAsync(beta_dev, beta_host, (size_t)n_beta * 8, hipMemcpyHostToDevice, ctx->stream));
     HIP_OR_FAIL(ctx, launch_thermo(d, beta_dev, n_beta, out_dev, ctx->stream));

@@ -112,6 +112,13 @@ hipError_t launch_check_levels(const SizeDev &s, hipStream_t st);
 
 // Most inverse temperatures one mc_thermo call takes.
 constexpr int kThermoMaxBetas = 1 << 20;
+// Most inverse temperatures one mc_thermo_static call takes (its device array
+// holds 5 doubles per inverse temperature: 320 KB per GPU).
+constexpr int kThermoStaticMaxBetas = 8192;
+constexpr int kMaxDevices = 64;
+// Device address of mc_thermo_static's array on `device` (which must be the
+// current device on the first call for it); looked up once per device.
+hipError_t thermo_scratch_address(int device, double **out);
 
 // Message returned by mc_last_error() on this thread (mc_api.hip).
 void set_last_error(const char *msg);

@@ -10,6 +10,8 @@
 //   E = sum p_m E_m,  C = beta^2 sum p_m (E_m - E)^2,
 //   F = -ln Z / beta, S = beta (E - F),  ln Z = ln sum D(m) exp(-beta E_m),
 // every sum taken in logarithms (shifted by its maximum) in binary64.
+#include <mutex>
+
 #include "mc_internal.h"
 
 namespace mcgpu {
@@ -88,6 +90,29 @@ __global__ __launch_bounds__(kThermoThreads) void k_thermo(SizeDev s, const doub
 hipError_t launch_thermo(const SizeDev &s, const double *beta_dev, int n_beta, double *out_dev, hipStream_t st) {
     hipLaunchKernelGGL(k_thermo, dim3(n_beta), dim3(kThermoThreads), 0, st, s, beta_dev, n_beta, out_dev);
     return hipGetLastError();
+}
+
+// Device memory of mc_thermo_static: the inverse temperatures and the four
+// results of at most kThermoStaticMaxBetas of them.  Every GPU the library
+// runs on holds its own copy of the array until the process ends.
+static __device__ __align__(256) double scratch[5 * kThermoStaticMaxBetas];
+
+// In host code `scratch` names a host-side stand-in, not the device array, so
+// its device address is looked up once per device, with that device current,
+// and kept; callers use only the address returned here.
+hipError_t thermo_scratch_address(int device, double **out) {
+    static std::mutex mu;
+    static double *addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = (double *)p;
+    }
+    *out = addr[device];
+    return hipSuccess;
 }
 
 }  // namespace mcgpu
