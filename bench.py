@@ -44,6 +44,7 @@ import time
 
 import numpy as np
 
+T_START = time.perf_counter()
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -99,6 +100,8 @@ def parse():
     ap.add_argument("--state-in", default=None, help="large: resume from this checkpoint")
     ap.add_argument("--state-out", default=None, help="large: checkpoint to this file after every iteration")
     ap.add_argument("--parts", type=int, default=4, help="large: launches per round (progress between them)")
+    ap.add_argument("--budget-s", type=float, default=None, help="large: start no iteration that would end after "
+                                                                  "this many seconds since the start")
     return ap.parse_args()
 
 
@@ -510,6 +513,9 @@ def bench_large(a, torch, mc):
     sweep_ms, step_s, flat_ratio = [], [], []
     t_all = time.perf_counter()
     for it in range(todo):
+        if a.budget_s and step_s and time.perf_counter() - T_START + 1.05 * max(step_s) > a.budget_s:
+            log("bench large: the next iteration would pass the time budget; stopping after %d" % it)
+            break
         t0 = time.perf_counter()
         ms = 0.0
         for k in range(parts):

@@ -867,7 +867,7 @@ __host__ __device__ inline BigLayout big_layout(int L, int n_bins, int r, int cp
     BigLayout o;
     o.tab = 0;
     o.pair = tab_lds ? align16((size_t)n_bins * (2 * r + 1) * 4) : 0;
-    o.ubuf = o.pair + 64 * 16;
+    o.ubuf = o.pair + 128 * 16;  // room for build_pair_parity_q (128 uint4); the others use 64
     o.total = o.ubuf + (size_t)2 * R * (L / 4) * cpb * 16;
     return o;
 }
@@ -1185,6 +1185,152 @@ __device__ __forceinline__ void bigq_row(uint32_t *lat, size_t P, int c, int y, 
     }
 }
 
+// ---- parity-state quad rows (bin_shift 1) ----------------------------------
+// With two levels per bin, a flip's threshold and the state it leads to depend
+// on the level only through its bin b and its parity p (m = 2b + p): a move by
+// d (|d| <= 2) goes to bin b + floor((p + d)/2).  The state is therefore kept
+// as S = B0 + 12 b + 2 p, the byte address of bin b's row {down, same, up} of
+// the per-bin table plus twice the parity (bit 1 of S is p; rows are
+// 4-aligned).  The threshold of a move by d from S is at
+// S - 2p + 4 (floor((p + d)/2) + 1), and the move takes S to
+// S + 12 floor((p + d)/2) + 2 ((p + d) & 1) - 2p: both are fixed offsets once
+// p is known, so the site-pair table holds them for p = 0 and p = 1 and a step
+// needs no bin arithmetic.
+
+// Byte offset, from S, of the threshold of a move by d from a level of parity p.
+__host__ __device__ constexpr int par_thr(int p, int d) {
+    return 4 * (((p + d + 4) >> 1) - 2 + 1) - 2 * p;
+}
+// Change of S when a move by d from parity p is accepted.
+__host__ __device__ constexpr int par_move(int p, int d) {
+    return 12 * (((p + d + 4) >> 1) - 2) + 2 * ((p + d) & 1) - 2 * p;
+}
+
+// Site-pair table of the parity-state step: entry i (the index of
+// build_pair_table) is 32 bytes, {X0, Y0, Z0, 0, X1, Y1, Z1, 0}: for a level
+// of parity p, Xp = {threshold of x+1 if x rejected, 0, 0, move if only x+1
+// accepted} and Yp / Zp (left neighbour x-1 not flipped / flipped) =
+// {threshold of x, move if only x accepted, threshold of x+1 if x accepted,
+// move if both accepted}, as signed byte offsets of S (the moves at odd bytes
+// for quad_move_selector's byte permutes).
+__device__ void build_pair_parity_q(uint4 *tbl, int tid, int nthreads) {
+    auto pack = [](int b0, int b1, int b2, int b3) {
+        return (uint32_t)(b0 & 255) | ((uint32_t)(b1 & 255) << 8) | ((uint32_t)(b2 & 255) << 16) |
+               ((uint32_t)(b3 & 255) << 24);
+    };
+    for (int e = tid; e < 128; e += nthreads) {
+        const int i = e >> 1, p = e & 1;
+        const int qx = (i & 1) + 2 * ((i >> 2) & 1);
+        const int qx1 = ((i >> 1) & 1) + 2 * ((i >> 3) & 1);
+        const int hx = (i >> 4) & 1, hx1 = (i >> 5) & 1;
+        const int d0 = 2 - (qx1 + hx1), d1 = 2 - (qx1 + (hx1 ^ 1));
+        uint32_t v[2];
+        for (int a = 0; a < 2; ++a) {
+            const int dx = 2 - (qx + (hx ^ a));
+            const int p1 = (p + dx) & 1;  // parity after x accepted
+            const int mx = par_move(p, dx);
+            v[a] = pack(par_thr(p, dx), mx, mx + par_thr(p1, d1), mx + par_move(p1, d1));
+        }
+        tbl[e] = make_uint4(pack(par_thr(p, d0), 0, 0, par_move(p, d0)), v[0], v[1], 0u);
+    }
+}
+
+// One row of a large lattice on a chain's quad, in the parity state (bin_shift
+// 1): the streamed words and quad exchange of bigq_row, with the thresholds
+// and moves of each pair taken at fixed offsets of S from the variant of its
+// entry for S's parity (the first pair of a step: the chain's parity; the
+// second: the parity each lane's assumed outcome of the first leaves).
+template <int L, bool TAB_LDS>
+__device__ __forceinline__ void bigq_row_p(uint32_t *lat, size_t P, int c, int y, uint32_t &S,
+                                           const uint32_t *tabc, uint32_t pair_addr, const uint4 *urow, int cpb,
+                                           uint32_t hym, uint32_t sel_h, uint32_t f0, uint32_t f1) {
+    static_assert(L % 4 == 0 && L > 64, "steps of four sites; at least three words per row");
+    constexpr int W = (L + 31) / 32;
+    constexpr int NB = L - 32 * (W - 1);
+    const int yu = y == 0 ? L - 1 : y - 1, yd = y + 1 == L ? 0 : y + 1;
+    auto word = [&](int yy, int w) { return lat + (size_t)(yy * W + w) * P + c; };
+    auto thr = [&](uint32_t off) { return big_threshold<TAB_LDS>(tabc, off); };
+    uint32_t cn = *word(y, 0), un = *word(yu, 0), dn = *word(yd, 0), cnn = *word(y, 1);
+    uint32_t carry = ((*word(y, W - 1) >> (NB - 1)) ^ cn) & 1u;
+    uint32_t c0new = 0u;
+    bool aprev = false;
+    for (int w = 0; w < W; ++w) {
+        const uint32_t cw = cn, uw = un, dw = dn;
+        const uint32_t cw1 = w + 1 < W ? cnn : c0new;
+        if (w + 1 < W) {
+            cn = cnn;
+            un = *word(yu, w + 1);
+            dn = *word(yd, w + 1);
+            if (w + 2 < W) cnn = *word(y, w + 2);
+        }
+        const int nb = w + 1 < W ? 32 : NB;
+        const uint32_t xu = cw ^ uw, xd = cw ^ dw, hb = cw ^ ((cw >> 1) | ((cw1 & 1u) << (nb - 1)));
+        const uint32_t P0 = __builtin_amdgcn_bitop3_b32(xu, xd, hb, 0x96);
+        const uint32_t P1 = __builtin_amdgcn_bitop3_b32(xu, xd, hb, 0xE8);
+        const uint32_t hs = (hb << 1) | carry;
+        carry = (hb >> 31) & 1u;
+        const uint4 *uw4 = urow + (size_t)w * 8 * cpb;
+        auto entry = [&](int p, uint4 &h0, uint4 &h1) {
+            const uint32_t idx = ((P0 >> (2 * p)) & 3u) | (((P1 >> (2 * p)) & 3u) << 2) | (((hs >> (2 * p)) & 3u) << 4);
+            const uint32_t a = pair_addr + idx * 32u;
+            h0 = lds_load96(a);
+            h1 = lds_load96(a + 16u);
+        };
+        uint32_t fw = 0u;
+        uint4 n0a, n0b, n1a, n1b;
+        entry(0, n0a, n0b);
+        entry(1, n1a, n1b);
+        const int nst = nb / 4;
+#pragma unroll
+        for (int st = 0; st < 8; ++st) {
+            if (st >= nst) break;
+            const int p = 2 * st;
+            const uint4 ea0 = n0a, ea1 = n0b, eb0 = n1a, eb1 = n1b;
+            if (st + 1 < nst) {
+                entry(p + 2, n0a, n0b);
+                entry(p + 3, n1a, n1b);
+            }
+            const uint4 u4 = uw4[st * cpb];
+            // the second pair's variants for this lane's assumed left neighbour
+            const uint32_t Yq0 = (eb0.z & hym) | (eb0.y & ~hym), Yq1 = (eb1.z & hym) | (eb1.y & ~hym);
+            // pair p from the chain's state
+            const bool pb = (S & 2u) != 0u;
+            const uint32_t ex = pb ? ea1.x : ea0.x;
+            const uint32_t V = aprev ? (pb ? ea1.z : ea0.z) : (pb ? ea1.y : ea0.y);
+            const uint32_t tx = thr(S + sbyte(V, 0));
+            const uint32_t t0 = thr(S + sbyte(ex, 0));
+            const uint32_t t1 = thr(S + sbyte(V, 2));
+            // pair p+1 from the state the assumed outcome of pair p leaves
+            const uint32_t mh = S + __builtin_amdgcn_perm(ex, V, sel_h);
+            const bool ph = (mh & 2u) != 0u;
+            const uint32_t exq = ph ? eb1.x : eb0.x;
+            const uint32_t Vq = ph ? Yq1 : Yq0;
+            const uint32_t qx = thr(mh + sbyte(Vq, 0));
+            const uint32_t q0 = thr(mh + sbyte(exq, 0));
+            const uint32_t q1 = thr(mh + sbyte(Vq, 2));
+            const bool bx = u4.z <= qx;
+            const uint32_t qn = bx ? q1 : q0;
+            const uint32_t nA = mh + (uint32_t)(bx ? sbyte(Vq, 3) : sbyte(exq, 3));
+            const uint32_t nB = mh + (uint32_t)(bx ? sbyte(Vq, 1) : 0);
+            const bool bx1 = u4.w <= qn;
+            const uint32_t res = (bx1 ? nA : nB) | (bx ? f1 : f0) | (bx1 ? 1u << 31 : 0u);
+            const uint32_t r0 = quad_bcast<0x00>(res), r1 = quad_bcast<0x55>(res);
+            const uint32_t r2 = quad_bcast<0xAA>(res), r3 = quad_bcast<0xFF>(res);
+            const bool ax = u4.x <= tx;
+            const uint32_t tn = ax ? t1 : t0;
+            const uint32_t rA = ax ? r3 : r2, rB = ax ? r1 : r0;
+            const bool ax1 = u4.y <= tn;
+            const uint32_t sel = ax1 ? rA : rB;
+            S = sel & 0x0FFFFFFFu;
+            fw |= (sel >> 28) << (4 * st);
+            aprev = (sel >> 31) != 0u;
+        }
+        const uint32_t cnew = cw ^ fw;
+        *word(y, w) = cnew;
+        if (w == 0) c0new = cnew;
+    }
+}
+
 // Chains per workgroup of the quad large-lattice kernel: up to two consumer
 // waves of 16 chains (the other waves produce), so that 8192 chains of L = 128
 // stay resident with the per-bin table in LDS.
@@ -1212,13 +1358,20 @@ __device__ __forceinline__ void sweep_tile_bigq(const SizeDev &s, int c0, int cp
     const bool active = consumer && cl < cpb && c < s.P;
     const bool lead = active && j == 0;  // one lane per chain for the trace, histogram and level
     const uint32_t hym = 0u - (uint32_t)((j >> 1) & 1);
-    const uint32_t sel_h = j == 0 ? kSelMove0 : j == 1 ? kSelMove1 : j == 2 ? kSelMove2 : kSelMove3;
+    // two levels per bin: the parity-state step (no bin arithmetic on the
+    // chain's path); one level per bin: levels and per-bin rows
+    const bool par = s.bin_shift == 1;
+    const uint32_t sel_h = par ? quad_move_selector((uint32_t)j)
+                               : j == 0 ? kSelMove0 : j == 1 ? kSelMove1 : j == 2 ? kSelMove2 : kSelMove3;
     const uint32_t f0 = (uint32_t)j << 28, f1 = f0 | (1u << 30);
     const uint32_t k0 = s.seed, k1 = (uint32_t)L;
     const uint32_t g0 = s.ctl->g;
     if (TAB_LDS)
         for (int i = threadIdx.x; i < s.n_bins * K; i += blockDim.x) stab[i] = s.tabc[i];
-    build_pair_levels_q(ptbl, threadIdx.x, blockDim.x);
+    if (par)
+        build_pair_parity_q(ptbl, threadIdx.x, blockDim.x);
+    else
+        build_pair_levels_q(ptbl, threadIdx.x, blockDim.x);
     const int np = (int)blockDim.x - 64 * nc, pt = (int)threadIdx.x - 64 * nc;
     const int per_sweep = L / R;
     const int64_t n_chunks = M * per_sweep;
@@ -1229,16 +1382,31 @@ __device__ __forceinline__ void sweep_tile_bigq(const SizeDev &s, int c0, int cp
     const int sB = r == 1 ? 3 : 4;  // log2(8 r)
     const int bs = s.bin_shift;
     const uint32_t pair_addr = (uint32_t)(size_t)(lds_u32 *)(ptbl);
+    // parity state S = T0 + 12 b + 2 p of level m = 2 b + p (T0: the table's
+    // byte address in LDS, or 0 for the table in global memory)
+    const uint32_t T0 = TAB_LDS ? (uint32_t)(size_t)(lds_u32 *)(stab) : 0u;
+    auto level_of = [&](uint32_t S) { return 2 * (int)((S - T0) / 12u) + (int)((S >> 1) & 1u); };
     int m = 0;
-    if (active) m = s.lev[c];
+    uint32_t S = 0u;
+    if (active) {
+        m = s.lev[c];
+        S = T0 + 12u * (uint32_t)(m >> 1) + 2u * (uint32_t)(m & 1);
+    }
     for (int64_t i = 0; i < n_chunks; ++i) {
         const int64_t k = i / per_sweep;
         const int y0 = (int)(i - k * per_sweep) * R;
         if (active) {
             const uint4 *ub = ubuf + (size_t)(i & 1) * chunk_words;
-            for (int rr = 0; rr < R; ++rr)
-                bigq_row<L, TAB_LDS>(s.lat, (size_t)s.P, c, y0 + rr, m, bs, B0, sB, s.tabc, pair_addr,
-                                     ub + (size_t)rr * (L / 4) * cpb + cl, cpb, hym, sel_h, f0, f1);
+            for (int rr = 0; rr < R; ++rr) {
+                const uint4 *urow = ub + (size_t)rr * (L / 4) * cpb + cl;
+                if (par)
+                    bigq_row_p<L, TAB_LDS>(s.lat, (size_t)s.P, c, y0 + rr, S, s.tabc, pair_addr, urow, cpb, hym,
+                                           sel_h, f0, f1);
+                else
+                    bigq_row<L, TAB_LDS>(s.lat, (size_t)s.P, c, y0 + rr, m, bs, B0, sB, s.tabc, pair_addr, urow,
+                                         cpb, hym, sel_h, f0, f1);
+            }
+            if (par && y0 + R == L) m = level_of(S);
             if (y0 + R == L && lead) {
                 const int ev = m - N / 2;
                 if (s.trace_bytes == 2)
