@@ -153,8 +153,9 @@ mc_status mc_run_chains_part(mc_ctx *ctx, int64_t n_sweeps, int64_t col, int64_t
                first), each position takes the chain not yet placed whose
                first configuration's level is nearest to the level the chain
                before it ended on, ties to the lower level, then the lower
-               index.  Mode 2 builds the order on the host from the trace's
-               first and last columns and synchronises.
+               index.  Mode 2 builds the order on the device (one
+               workgroup, from the trace's first and last columns), so it
+               does not synchronise and can be captured in a graph.
    The test of chain c's k-th configuration uses its own random word (round,
    c, k) in every mode, whatever c's position.
    Errors: MC_EINVAL, MC_ESTATE (no complete round of mc_run_chains to join),
@@ -336,7 +337,8 @@ mc_status mc_autotune(mc_ctx *ctx, int64_t probe_sweeps, int32_t *chains_per_blo
    calls) are baked into the graph and must stay allocated; hist_dev must hold
    zeros before the first replay (each update leaves them zeroed).  A graph
    can only be created and launched right after a weight update (or at the
-   start).  Destroy graphs before their context.
+   start).  mode: the joint's mode (0, 1 or 2), as for mc_join.  Destroy
+   graphs before their context.
    Errors: MC_EINVAL, MC_ESTATE, MC_EOVERFLOW (n_chains * n_sweeps >= 2^31;
    at launch, also when a replay would pass the 2^32 sweep or joint-round
    counters of the random words). */

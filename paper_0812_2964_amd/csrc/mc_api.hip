@@ -114,6 +114,7 @@ void free_size(SizeDev &d) {
     if (d.join_order) (void)hipFree(d.join_order);
     if (d.hist64) (void)hipFree(d.hist64);
     if (d.n_bad) (void)hipFree(d.n_bad);
+    if (d.ord) (void)hipFree(d.ord);
     d = SizeDev{};
 }
 
@@ -330,62 +331,6 @@ hipError_t autotune_batched(mc_ctx *ctx, int64_t probe_sweeps, hipEvent_t e0, hi
 
 }  // namespace
 
-// The energy ordering of the chains for one joint (the paper suggests ordering
-// the nodes by the energies of their configurations, Sec. 2, and leaves the
-// rule open): a greedy chain of nearest levels.  Starting from the seam (with
-// none, chain 0 goes first), each position takes the chain not yet placed
-// whose first level is nearest to the last level of the chain before it,
-// ties to the lower level, then the lower index.  O(P log P).
-static void energy_order(int P, const std::vector<int> &first, const std::vector<int> &last, int sigma,
-                         std::vector<int32_t> &order) {
-    std::set<std::pair<int, int>> left;
-    for (int c = 0; c < P; ++c) left.insert({first[c], c});
-    order.assign((size_t)P, 0);
-    int t = 0, ref = sigma;
-    if (ref < 0 && P > 0) {
-        order[t++] = 0;
-        left.erase({first[0], 0});
-        ref = last[0];
-    }
-    for (; t < P; ++t) {
-        auto up = left.lower_bound({ref, -1});  // nearest level >= ref, lowest index
-        auto pick = up;
-        if (up != left.begin()) {
-            const int below = std::prev(up)->first;
-            auto lo = left.lower_bound({below, -1});  // level below ref, lowest index
-            if (up == left.end() || ref - below <= up->first - ref) pick = lo;
-        }
-        order[t] = pick->second;
-        ref = last[pick->second];
-        left.erase(pick);
-    }
-}
-
-// The first and last levels of every chain's trace of one round (synchronising).
-static hipError_t trace_ends(mc_ctx *ctx, const SizeDev &d, const void *trace_dev, int64_t M, std::vector<int> &first,
-                             std::vector<int> &last) {
-    const size_t eb = (size_t)d.trace_bytes;
-    std::vector<char> a((size_t)d.P * eb), b((size_t)d.P * eb);
-    const char *t = (const char *)trace_dev;
-    hipError_t e = hipMemcpy2DAsync(a.data(), eb, t, (size_t)M * eb, eb, (size_t)d.P, hipMemcpyDeviceToHost, ctx->stream);
-    if (e == hipSuccess)
-        e = hipMemcpy2DAsync(b.data(), eb, t + (size_t)(M - 1) * eb, (size_t)M * eb, eb, (size_t)d.P,
-                             hipMemcpyDeviceToHost, ctx->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-    if (e != hipSuccess) return e;
-    first.resize((size_t)d.P);
-    last.resize((size_t)d.P);
-    auto level = [&](const char *q) {
-        const int v = eb == 2 ? (int)*(const int16_t *)q : (int)*(const int32_t *)q;
-        return std::min(std::max(v + d.N / 2, 0), d.N);
-    };
-    for (int c = 0; c < d.P; ++c) {
-        first[c] = level(a.data() + (size_t)c * eb);
-        last[c] = level(b.data() + (size_t)c * eb);
-    }
-    return hipSuccess;
-}
-
 // CRC-32 of the IEEE 802.3 / zlib definition (reflected polynomial
 // 0xEDB88320, initial and final complement), table driven.
 static uint32_t crc32_of(const unsigned char *p, size_t n) {
@@ -536,7 +481,8 @@ mc_status mc_create(const mc_size *sizes, int32_t n_sizes, void *hip_stream, mc_
             hipMalloc((void **)&d.scratch_cut, (size_t)d.P * 4) != hipSuccess ||
             hipMalloc((void **)&d.join_order, (size_t)d.P * 4) != hipSuccess ||
             hipMalloc((void **)&d.hist64, (size_t)d.n_bins * 8) != hipSuccess ||
-            hipMalloc((void **)&d.n_bad, sizeof(int64_t)) != hipSuccess) {
+            hipMalloc((void **)&d.n_bad, sizeof(int64_t)) != hipSuccess ||
+            hipMalloc((void **)&d.ord, order_scratch_ints(d.N, d.P) * 4) != hipSuccess) {
             (void)hipGetLastError();
             st = fail(MC_ENOMEM, "device allocation failed for size %d", i);
             break;
@@ -678,16 +624,7 @@ mc_status mc_join(mc_ctx *ctx, int32_t i, const void *trace_dev, int64_t n_sweep
         return fail(MC_EINVAL, "n_sweeps=%lld differs from the last run (%lld)", (long long)n_sweeps, (long long)h.last_M);
     const int32_t *order = nullptr;
     if (mode == 2) {
-        std::vector<int> first, last;
-        HIP_OR_FAIL(ctx, trace_ends(ctx, h.dev, trace_dev, n_sweeps, first, last));
-        Ctl c{};
-        HIP_OR_FAIL(ctx, hipMemcpyAsync(&c, h.dev.ctl, sizeof c, hipMemcpyDeviceToHost, ctx->stream));
-        HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
-        std::vector<int32_t> ord;
-        energy_order(h.dev.P, first, last, c.sigma, ord);
-        HIP_OR_FAIL(ctx, hipMemcpyAsync(h.dev.join_order, ord.data(), ord.size() * 4, hipMemcpyHostToDevice,
-                                        ctx->stream));
-        HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+        HIP_OR_FAIL(ctx, launch_energy_order(h.dev, trace_dev, n_sweeps, ctx->stream));
         order = h.dev.join_order;
     }
     HIP_OR_FAIL(ctx, launch_join(h.dev, trace_dev, n_sweeps, cut_dev, hist_dev, mode == 2 ? 0 : mode, order,
@@ -1175,7 +1112,7 @@ mc_status mc_graph_create(mc_ctx *ctx, int64_t n_sweeps, int32_t n_iters, void *
     if (st != MC_OK) return st;
     if (n_sweeps < 1 || n_sweeps > 0x7FFFFFFF) return fail(MC_EINVAL, "n_sweeps must be 1..2^31-1");
     if (n_iters < 1 || n_iters > 100000) return fail(MC_EINVAL, "n_iters must be 1..100000");
-    if (mode != 0 && mode != 1) return fail(MC_EINVAL, "mode must be 0 or 1");
+    if (mode < 0 || mode > 2) return fail(MC_EINVAL, "mode must be 0, 1 or 2");
     if (!trace_dev || !hist_dev || !cut_dev) return fail(MC_EINVAL, "null pointer array");
     const int n = (int)ctx->sizes.size();
     for (int i = 0; i < n; ++i) {
@@ -1198,8 +1135,13 @@ mc_status mc_graph_create(mc_ctx *ctx, int64_t n_sweeps, int32_t n_iters, void *
     hipError_t e = hipSuccess;
     for (int it = 0; it < n_iters && e == hipSuccess; ++it) {
         e = enqueue_sweeps(ctx, cs, n_sweeps, n_sweeps, trace_dev, hist_dev);
-        for (int i = 0; i < n && e == hipSuccess; ++i)
-            e = launch_join(ctx->sizes[i].dev, trace_dev[i], n_sweeps, cut_dev[i], hist_dev[i], mode, nullptr, cs);
+        for (int i = 0; i < n && e == hipSuccess; ++i) {
+            const SizeDev &d = ctx->sizes[i].dev;
+            if (mode == 2) e = launch_energy_order(d, trace_dev[i], n_sweeps, cs);
+            if (e == hipSuccess)
+                e = launch_join(d, trace_dev[i], n_sweeps, cut_dev[i], hist_dev[i], mode == 2 ? 0 : mode,
+                                mode == 2 ? d.join_order : nullptr, cs);
+        }
         for (int i = 0; i < n && e == hipSuccess; ++i) e = launch_update(ctx->sizes[i].dev, hist_dev[i], cs);
     }
     hipGraph_t graph = nullptr;

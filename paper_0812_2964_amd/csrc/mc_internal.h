@@ -49,7 +49,21 @@ struct SizeDev {
     int32_t *join_order;    // [P] chain at each position of an energy-ordered joint
     int64_t *hist64;        // [n_bins] joined histogram of Algorithm step 6's rounds
     int64_t *n_bad;         // [1] chains whose level disagrees with their lattice (mc_check_levels)
+    int32_t *ord;           // [order_scratch_ints(N, P)] scratch of the energy ordering (k_energy_order)
 };
+
+// Scratch of the device-side energy ordering of one size: per level the next
+// and the end position of its run (2 (N+1)), the chains sorted by first level
+// and index, every chain's first and last level (3 P), then, 8-aligned, the
+// bitmap of levels with unplaced chains and its summary (uint64 words).
+__host__ __device__ inline int order_bitmap_words(int N) { return (N + 64) / 64; }
+__host__ __device__ inline int order_summary_words(int N) { return (order_bitmap_words(N) + 63) / 64; }
+__host__ __device__ inline size_t order_bitmap_at(int N, int P) {
+    return ((size_t)2 * (N + 1) + (size_t)3 * P + 1) & ~(size_t)1;  // in int32 units, 8-byte aligned
+}
+__host__ __device__ inline size_t order_scratch_ints(int N, int P) {
+    return order_bitmap_at(N, P) + 2 * (size_t)(order_bitmap_words(N) + order_summary_words(N));
+}
 
 // How the sweeps of one size are launched.
 enum SweepKind : int32_t {
@@ -73,6 +87,8 @@ struct SizePlan {
 };
 
 constexpr int kMaxSizes = 16;
+// Levels of the largest lattice (L = 256: N + 1).
+constexpr int kMaxLevels = 256 * 256 + 1;
 
 // One unit of work of the batched launch: chains c0 .. c0+cpb-1 of size `size`.
 struct Tile {
@@ -98,6 +114,8 @@ hipError_t launch_sweeps_batched(const SizeDev *sizes, const SizePlan *plans, in
                                  int n_tiles, int32_t *counter_dev, int grid, size_t lds_bytes, int64_t M, int64_t ld,
                                  void *const *trace, int32_t *const *hist, hipStream_t st);
 hipError_t launch_advance(const SizeDev &s, int64_t M, hipStream_t st);
+// The energy ordering of a round's chains into s.join_order (k_energy_order).
+hipError_t launch_energy_order(const SizeDev &s, const void *trace, int64_t M, hipStream_t st);
 // order: the chain at each position of the joint, or nullptr for index order.
 hipError_t launch_join(const SizeDev &s, const void *trace, int64_t M, int32_t *cut, int32_t *hist, int mode,
                        const int32_t *order, hipStream_t st);

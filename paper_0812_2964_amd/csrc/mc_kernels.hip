@@ -169,7 +169,10 @@ __device__ __forceinline__ void sweep_row(uint32_t y, uint32_t g, uint32_t c, ui
     int D = 16 - 8 * anti;
     uint32_t f0 = 0;
     uint4 rnd = make_uint4(0, 0, 0, 0);
-#pragma unroll
+    // fully unrolled up to L = 64 (the row's words and bit positions become
+    // constants); larger rows by 32 sites, within the instruction cache
+    constexpr int kUnrollSites = L <= 64 ? L : 32;
+#pragma unroll kUnrollSites
     for (int x = 0; x < L; ++x) {
         if ((x & 3) == 0)
             rnd = philox10(make_uint4(y * (uint32_t)(L / 4) + (uint32_t)(x >> 2), g, c, kDomSweep), k0, k1);
@@ -2024,6 +2027,181 @@ __global__ __launch_bounds__(256) void k_join_hist(JoinParams p) {
         for (int64_t k = threadIdx.x; k < ndisc; k += blockDim.x)
             atomicSub(&p.hist[min(max((int)row[k] + half, 0), s.N) >> s.bin_shift], 1);
     }
+}
+
+// ---------------------------------------------------------------------------
+// The energy ordering of the chains for a joint (Sec. 2 suggests ordering the
+// nodes by the energies of their configurations and leaves the rule open): a
+// greedy chain of nearest levels.  Starting from the seam (with none, chain 0
+// goes first), each position takes the chain not yet placed whose first
+// configuration's level is nearest to the level the chain before it ended on,
+// ties to the lower level, then the lower index.  Built on the device, so a
+// joint in energy order needs no host round trip and can be captured in a
+// graph.  One workgroup:
+//   (1) every chain's first and last level; counts of first levels and their
+//       prefix sums, the runs of a list of chains sorted by (first level,
+//       index);
+//   (2) the list, filled in index order a chunk at a time (a chain's place in
+//       its level's run is the number of earlier chains of that level);
+//   (3) a two-level bitmap (in LDS) of the levels that still hold unplaced
+//       chains;
+//   (4) one thread walks the positions: the nearest level at or above the
+//       reference and the nearest one below it come from the bitmaps; the
+//       pick takes the next chain of that level's run.
+// ---------------------------------------------------------------------------
+constexpr int kOrderThreads = 256;
+constexpr int kOrderMaxWords = (kMaxLevels + 64) / 64;
+
+template <typename TT>
+__global__ __launch_bounds__(kOrderThreads) void k_energy_order(SizeDev s, const TT *tr, int64_t M) {
+    const int N = s.N, P = s.P, half = N / 2, t = threadIdx.x;
+    int32_t *nextp = s.ord, *endp = s.ord + (N + 1), *list = s.ord + 2 * (N + 1);
+    int32_t *firstl = list + P, *lastl = firstl + P;
+    const int NW = order_bitmap_words(N), NSUM = order_summary_words(N);
+    __shared__ uint64_t bm[kOrderMaxWords];
+    __shared__ uint64_t sm[(kOrderMaxWords + 63) / 64];
+    __shared__ int32_t sh[kOrderThreads];
+    __shared__ int32_t sf[kOrderThreads];
+    for (int m = t; m <= N; m += kOrderThreads) nextp[m] = 0;
+    for (int c = t; c < P; c += kOrderThreads) {
+        firstl[c] = min(max((int)tr[(size_t)c * M] + half, 0), N);
+        lastl[c] = min(max((int)tr[(size_t)c * M + (M - 1)] + half, 0), N);
+    }
+    __syncthreads();
+    for (int c = t; c < P; c += kOrderThreads) atomicAdd(&nextp[firstl[c]], 1);
+    __syncthreads();
+    // exclusive prefix sums of the counts, each thread over a contiguous range
+    const int per = (N + 1 + kOrderThreads - 1) / kOrderThreads;
+    const int m0 = min(N + 1, t * per), m1 = min(N + 1, m0 + per);
+    int tot = 0;
+    for (int m = m0; m < m1; ++m) tot += nextp[m];
+    sh[t] = tot;
+    __syncthreads();
+    if (t == 0) {
+        int acc = 0;
+        for (int i = 0; i < kOrderThreads; ++i) {
+            const int v = sh[i];
+            sh[i] = acc;
+            acc += v;
+        }
+    }
+    __syncthreads();
+    int acc = sh[t];
+    for (int m = m0; m < m1; ++m) {
+        const int v = nextp[m];
+        nextp[m] = acc;
+        endp[m] = acc + v;
+        acc += v;
+    }
+    __syncthreads();
+    // the sorted list, stable in the chain index
+    for (int c0 = 0; c0 < P; c0 += kOrderThreads) {
+        const int c = c0 + t;
+        const int f = c < P ? firstl[c] : -1;
+        sf[t] = f;
+        __syncthreads();
+        int rank = 0;
+        bool lastof = true;
+        if (f >= 0) {
+            for (int u = 0; u < kOrderThreads; ++u) {
+                if (sf[u] != f) continue;
+                if (u < t) ++rank;
+                if (u > t) lastof = false;
+            }
+            list[nextp[f] + rank] = c;
+        }
+        __syncthreads();
+        if (f >= 0 && lastof) nextp[f] += rank + 1;
+        __syncthreads();
+    }
+    // back to the start of every run (runs are contiguous in level order)
+    for (int m = t; m <= N; m += kOrderThreads) nextp[m] = m > 0 ? endp[m - 1] : 0;
+    for (int w = t; w < NW; w += kOrderThreads) {
+        uint64_t bits = 0;
+        for (int k = 0; k < 64; ++k) {
+            const int m = 64 * w + k;
+            if (m <= N && endp[m] > (m > 0 ? endp[m - 1] : 0)) bits |= 1ull << k;
+        }
+        bm[w] = bits;
+    }
+    __syncthreads();
+    for (int w = t; w < NSUM; w += kOrderThreads) {
+        uint64_t bits = 0;
+        for (int k = 0; k < 64; ++k)
+            if (64 * w + k < NW && bm[64 * w + k]) bits |= 1ull << k;
+        sm[w] = bits;
+    }
+    __syncthreads();
+    if (t != 0) return;
+    auto take = [&](int m) {
+        const int c = list[nextp[m]];
+        nextp[m] += 1;
+        if (nextp[m] == endp[m]) {
+            const int w = m >> 6;
+            bm[w] &= ~(1ull << (m & 63));
+            if (!bm[w]) sm[w >> 6] &= ~(1ull << (w & 63));
+        }
+        return c;
+    };
+    // smallest level >= m that holds unplaced chains, or -1
+    auto at_or_above = [&](int m) {
+        if (m > N) return -1;
+        int w = m >> 6;
+        const uint64_t b = bm[w] & (~0ull << (m & 63));
+        if (b) return 64 * w + __ffsll((unsigned long long)b) - 1;
+        const int w1 = w + 1;
+        int sw = w1 >> 6;
+        if (sw >= NSUM) return -1;
+        uint64_t sb = sm[sw] & (~0ull << (w1 & 63));
+        while (!sb) {
+            if (++sw >= NSUM) return -1;
+            sb = sm[sw];
+        }
+        w = 64 * sw + __ffsll((unsigned long long)sb) - 1;
+        return 64 * w + __ffsll((unsigned long long)bm[w]) - 1;
+    };
+    // largest level <= m that holds unplaced chains, or -1
+    auto at_or_below = [&](int m) {
+        if (m < 0) return -1;
+        int w = m >> 6;
+        const int k = m & 63;
+        const uint64_t b = bm[w] & (k == 63 ? ~0ull : ((1ull << (k + 1)) - 1));
+        if (b) return 64 * w + 63 - __clzll((long long)b);
+        const int w1 = w - 1;
+        if (w1 < 0) return -1;
+        int sw = w1 >> 6;
+        const int k1 = w1 & 63;
+        uint64_t sb = sm[sw] & (k1 == 63 ? ~0ull : ((1ull << (k1 + 1)) - 1));
+        while (!sb) {
+            if (--sw < 0) return -1;
+            sb = sm[sw];
+        }
+        w = 64 * sw + 63 - __clzll((long long)sb);
+        return 64 * w + 63 - __clzll((long long)bm[w]);
+    };
+    int pos = 0, ref = s.ctl->sigma;
+    if (ref < 0 && P > 0) {
+        const int c = take(firstl[0]);  // chain 0 heads its level's run
+        s.join_order[pos++] = c;
+        ref = lastl[c];
+    }
+    for (; pos < P; ++pos) {
+        const int up = at_or_above(ref);
+        const int dn = at_or_below(ref - 1);
+        const int pick = (dn >= 0 && (up < 0 || ref - dn <= up - ref)) ? dn : up;
+        const int c = take(pick);
+        s.join_order[pos] = c;
+        ref = lastl[c];
+    }
+}
+
+hipError_t launch_energy_order(const SizeDev &s, const void *trace, int64_t M, hipStream_t st) {
+    if (s.N > kMaxLevels - 1) return hipErrorInvalidValue;
+    if (s.trace_bytes == 2)
+        hipLaunchKernelGGL(k_energy_order<int16_t>, dim3(1), dim3(kOrderThreads), 0, st, s, (const int16_t *)trace, M);
+    else
+        hipLaunchKernelGGL(k_energy_order<int32_t>, dim3(1), dim3(kOrderThreads), 0, st, s, (const int32_t *)trace, M);
+    return hipGetLastError();
 }
 
 template <typename TT>

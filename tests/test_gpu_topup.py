@@ -29,10 +29,13 @@ def _weight(L, bs, seed, amp=3.0):
     return -0.5 * L * L * x * x + rng.normal(0, amp, nb)
 
 
-@pytest.mark.parametrize("L,P,M,bs", [(8, 16, 30, 1), (16, 100, 20, 0), (32, 1500, 8, 1)])
+@pytest.mark.parametrize("L,P,M,bs", [(8, 16, 30, 1), (16, 100, 20, 0), (32, 1500, 8, 1), (100, 700, 2, 1),
+                                      (256, 33, 1, 0)])
 def test_energy_ordered_joint_bitexact(L, P, M, bs):
-    """Several rounds of sweeps and mode-2 joints; 1500 chains cross the
-    serial fix-up's chunk of 1024 positions."""
+    """Several rounds of sweeps and mode-2 joints (the order built on the
+    device); 1500 chains cross the serial fix-up's chunk of 1024 positions
+    and the ordering's chunks of 256; L = 256 has int32 traces and 65537
+    levels (the ordering's bitmaps at their largest)."""
     import torch
 
     mc = _mc()
@@ -57,6 +60,41 @@ def test_energy_ordered_joint_bitexact(L, P, M, bs):
     assert ret == oret and flat == oflat
     assert np.array_equal(w2.view(np.uint64), R.lnW.view(np.uint64))
     ctx.close()
+
+
+def test_energy_ordered_graph_replays_equal_eager_iterations():
+    """Iterations with energy-ordered joints captured in a graph (the order
+    is built on the device, so the whole iteration is captured) equal the
+    same iterations made eagerly, bit for bit, with eager work between the
+    replays."""
+    import torch
+
+    mc = _mc()
+    L, P, M, bs = 16, 200, 40, 1
+    w = _weight(L, bs, 3)
+    a = mc.Context([(L, P, 5, bs)])
+    b = mc.Context([(L, P, 5, bs)])
+    a.init_weights(w)
+    b.init_weights(w)
+    tr, h, cut = a.new_trace(M), a.new_hist(), a.new_cut()
+    g = a.graph(M, 2, [tr], [h], [cut], mode=2)
+    for rep in range(3):
+        g.launch()
+        a.sync()
+        scratch = torch.ones(1 << 20, device="cuda").sum()  # eager work between replays
+        for it in range(2):
+            tb, hb, cb = b.new_trace(M), b.new_hist(), b.new_cut()
+            b.run_chains(M, tb, hb)
+            b.join(tb, cb, hb, mode=2)
+            b.update_weights(hb, want=False)
+        assert float(scratch) == float(1 << 20)
+        assert np.array_equal(tr.cpu().numpy(), tb.cpu().numpy()), rep
+        assert np.array_equal(cut.cpu().numpy(), cb.cpu().numpy()), rep
+        assert np.array_equal(a.weights().view(np.uint64), b.weights().view(np.uint64)), rep
+        assert a.counters() == b.counters() and np.array_equal(a.levels(), b.levels())
+    g.close()
+    a.close()
+    b.close()
 
 
 @pytest.mark.parametrize("mode", [0, 2])
