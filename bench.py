@@ -67,10 +67,10 @@ BATCHED_LS = [16, 24, 32, 48, 64]
 # counted in the compiled code of the step (the instructions between two
 # selections of the quad's result in the unrolled row loop): the quad kernel
 # (kind 7, in the batched launch at L = 64 and alone at L = 32) and the
-# large-lattice quad kernel (kinds 8, 9 at L = 128).  A chain's attempts are
+# large-lattice quad kernel in the parity state (kinds 8, 9 at L = 128).  A chain's attempts are
 # serial and its wave issues one VALU instruction per issue interval at best,
 # so 4 sites take at least valu_per_step x interval cycles.
-CONSUMER_VALU_PER_STEP = {7: 37, 8: 71, 9: 71}
+CONSUMER_VALU_PER_STEP = {7: 37, 8: 60, 9: 60}
 
 
 def log(msg):
@@ -139,12 +139,12 @@ def issue_interval(mc):
     return cyc, cycles / sec
 
 
-def chain_ceiling(mc, kinds, attempts_per_launch, serial_attempts):
+def chain_ceiling(mc, kind, attempts_per_launch, serial_attempts):
     """The ceiling serial chains put on one launch: the chain with the most
-    attempts (serial_attempts = sweeps x sites of the largest lattice) cannot
-    finish before its consumer wave has issued valu_per_step VALU
-    instructions per four sites, one per issue interval at best."""
-    kind = max(kinds, key=lambda k: CONSUMER_VALU_PER_STEP.get(k, 0))
+    attempts (serial_attempts = sweeps x sites of the largest lattice, run by
+    kernel kind `kind`) cannot finish before its consumer wave has issued
+    valu_per_step VALU instructions per four sites, one per issue interval at
+    best.  None for kinds whose step is not counted."""
     if kind not in CONSUMER_VALU_PER_STEP:
         return None
     t, f = issue_interval(mc)
@@ -428,7 +428,7 @@ def bench_batched(a, torch, mc):
     res["roofline"]["kernel"] = "k_sweep_batched (mc_run_chains, one persistent launch of the five sizes)"
     res["roofline"]["kernel_ms_basis"] = ("HIP events around each graph replay on the context's stream: the sweep "
                                           "launch plus the joints and updates of the five sizes (a few ms)")
-    cc = chain_ceiling(mc, [p_[1] for p_ in plans], att, M * max(Ls) ** 2)
+    cc = chain_ceiling(mc, plans[Ls.index(max(Ls))][1], att, M * max(Ls) ** 2)
     if cc is not None:
         cc["frac"] = (att / launch_s) / cc["attempts_per_s"]
         res["roofline"]["chain_ceiling"] = cc
@@ -477,6 +477,10 @@ def bench_l128(a, torch, mc):
                        "L": L, "chains": P, "sweeps_per_step": M, "kernel_kind": kind})
     res["roofline"] = roofline(att, sweep_s, None)
     res["roofline"]["kernel"] = kernel_name(kind, L) + " (mc_run_chains)"
+    cc = chain_ceiling(mc, kind, att, M * L * L)
+    if cc is not None:
+        cc["frac"] = (att / sweep_s) / cc["attempts_per_s"]
+        res["roofline"]["chain_ceiling"] = cc
     res["sweep_attempts_per_s"] = att / sweep_s
     return res
 
@@ -567,6 +571,10 @@ def bench_large(a, torch, mc):
         sweep_s = sum(sweep_ms) / n / 1e3
         res["roofline"] = roofline(att, sweep_s, None)
         res["roofline"]["kernel"] = kernel_name(kind, L) + " (mc_run_chains_part, %d launches per round)" % parts
+        cc = chain_ceiling(mc, kind, att, M * N)
+        if cc is not None:
+            cc["frac"] = (att / sweep_s) / cc["attempts_per_s"]
+            res["roofline"]["chain_ceiling"] = cc
         res["sweep_attempts_per_s"] = att / sweep_s
     res["iterations_done"] = st["updates"]
     res["iterations_to_flat"] = st["first_flat"] or None

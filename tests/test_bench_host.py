@@ -110,3 +110,24 @@ def test_record_carries_the_contract_keys():
     assert abs(r["peak"] - 256 * 128 * 2.4e9 / 1e12) < 1e-9
     assert abs(r["achieved"] - 31 * 4.194304e11 / 3.5 / 1e12) < 1e-9
     assert abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-12
+
+
+def test_chain_ceiling_from_the_issue_interval():
+    """The chain ceiling of a launch: the longest chain issues valu_per_step
+    instructions per four sites at one per issue interval, so a launch of A
+    attempts whose longest chain makes S of them takes at least
+    S x valu x interval / 4 cycles.  A stub stands in for the probe."""
+    import bench
+
+    class Probe:
+        def probe(self, kind, iters):
+            assert kind == 8
+            return 4.0, 1.0, 0, 2.4e9  # 4 cycles per instruction; a 2.4 GHz clock over 1 s
+
+    A, S = 1.0e12, 4.0e8
+    cc = bench.chain_ceiling(Probe(), 7, A, S)
+    floor = bench.CONSUMER_VALU_PER_STEP[7] * 4.0 / 4.0
+    assert cc["cycles_per_attempt_floor"] == floor and cc["kernel_kind"] == 7
+    assert abs(cc["attempts_per_s"] - A / (S * floor / bench.CLOCK_HZ)) <= 1e-9 * cc["attempts_per_s"]
+    assert abs(cc["probe_clock_hz"] - 2.4e9) < 1.0
+    assert bench.chain_ceiling(Probe(), 3, A, S) is None  # the bit-by-bit kind has no counted step
