@@ -145,31 +145,40 @@ __global__ __launch_bounds__(256) void k_mlp_backward(const float *p, const floa
     }
 }
 
-// Gradient of every parameter: one thread each, summing over the samples in order.
-__global__ __launch_bounds__(256) void k_mlp_wgrad(const float *x, int n, const float *act, const float *dact,
-                                                   const float *dy, float *grad) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= N_PARAMS) return;
+// Gradient of every parameter: one wave per parameter.  Lane l sums samples
+// l, l + 64, l + 128, ... in order, then the wave adds its 64 partial sums in
+// a fixed butterfly, so the result depends on n alone, not on the launch.
+// The sample loops are over rows of the activations (2H floats each, held in
+// L2 for the sample counts of a training set).
+constexpr int kWgradWaves = 4;
+
+__global__ __launch_bounds__(64 * kWgradWaves) void k_mlp_wgrad(const float *x, int n, const float *act,
+                                                                const float *dact, const float *dy, float *grad) {
+    const int k = blockIdx.x * kWgradWaves + (int)(threadIdx.x >> 6);
+    const int lane = (int)(threadIdx.x & 63);
+    if (k >= N_PARAMS) return;  // the whole wave leaves together
     float acc = 0.f;
     if (k < OFF_B1) {  // W1[i][c]
         const int i = k >> 1, c = k & 1;
-        for (int s = 0; s < n; ++s) acc += dact[(size_t)s * 2 * H + i] * x[2 * s + c];
+        for (int s = lane; s < n; s += 64) acc += dact[(size_t)s * 2 * H + i] * x[2 * s + c];
     } else if (k < OFF_W2) {  // b1[i]
         const int i = k - OFF_B1;
-        for (int s = 0; s < n; ++s) acc += dact[(size_t)s * 2 * H + i];
+        for (int s = lane; s < n; s += 64) acc += dact[(size_t)s * 2 * H + i];
     } else if (k < OFF_B2) {  // W2[j][i]
         const int j = (k - OFF_W2) / H, i = (k - OFF_W2) % H;
-        for (int s = 0; s < n; ++s) acc += dact[(size_t)s * 2 * H + H + j] * act[(size_t)s * 2 * H + i];
+        for (int s = lane; s < n; s += 64) acc += dact[(size_t)s * 2 * H + H + j] * act[(size_t)s * 2 * H + i];
     } else if (k < OFF_W3) {  // b2[j]
         const int j = k - OFF_B2;
-        for (int s = 0; s < n; ++s) acc += dact[(size_t)s * 2 * H + H + j];
+        for (int s = lane; s < n; s += 64) acc += dact[(size_t)s * 2 * H + H + j];
     } else if (k < OFF_B3) {  // W3[j]
         const int j = k - OFF_W3;
-        for (int s = 0; s < n; ++s) acc += dy[s] * act[(size_t)s * 2 * H + H + j];
+        for (int s = lane; s < n; s += 64) acc += dy[s] * act[(size_t)s * 2 * H + H + j];
     } else {  // b3
-        for (int s = 0; s < n; ++s) acc += dy[s];
+        for (int s = lane; s < n; s += 64) acc += dy[s];
     }
-    grad[k] = acc;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) grad[k] = acc;
 }
 
 // Adam (Kingma & Ba), bias-corrected.
@@ -263,7 +272,8 @@ mc_status loss_grad(const float *p, const float *x, const float *t, const float 
     hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(256), 0, st, s.y, t, w, n, s.scal);
     hipLaunchKernelGGL(k_mlp_backward, dim3(blocks(n, 256)), dim3(256), 0, st, p, t, w, n, s.scal, s.y, s.act,
                        s.dact, s.dy);
-    hipLaunchKernelGGL(k_mlp_wgrad, dim3(blocks(N_PARAMS, 256)), dim3(256), 0, st, x, n, s.act, s.dact, s.dy, grad);
+    hipLaunchKernelGGL(k_mlp_wgrad, dim3(blocks(N_PARAMS, kWgradWaves)), dim3(64 * kWgradWaves), 0, st, x, n, s.act,
+                       s.dact, s.dy, grad);
     MLP_HIP(hipGetLastError());
     return MC_OK;
 }

@@ -42,6 +42,25 @@ def test_forward_and_gradient_match_fp64_oracle():
     assert np.abs(g - g64).max() <= 1e-3 * np.abs(g64).max()
 
 
+@pytest.mark.parametrize("n", [1, 63, 65, 10917])
+def test_gradient_at_ragged_and_large_sample_counts(n):
+    """The gradient's sample loop (one wave per parameter, 64 lanes over the
+    samples) at one sample, either side of a wave's width, and the sample
+    count of training on L in {8, 16, 32, 64, 128} (10917 bins)."""
+    import torch
+
+    mc = _mc()
+    params, x, t, w = _problem(n, seed=n)
+    net = mc.MLP(params=params)
+    xd, td, wd = (torch.from_numpy(a).cuda() for a in (x, t, w))
+    loss, g = net.loss_grad(xd, td, wd)
+    l64, g64 = O.mlp_loss_grad(params.astype(np.float64), x.astype(np.float64), t.astype(np.float64),
+                               w.astype(np.float64))
+    assert abs(float(loss.item()) - l64) <= 1e-4 * l64
+    g = g.cpu().numpy()
+    assert np.abs(g - g64).max() <= 1e-3 * np.abs(g64).max()
+
+
 def test_adam_steps_match_reference():
     import torch
 
