@@ -681,9 +681,11 @@ def bench_learned256(a, torch, mc):
 
 def bench_peaks(a, torch, mc):
     """The microbenchmarks of mc_probe: chip-wide VALU rates of the attempt's
-    instruction classes, LDS bandwidth, dependent LDS read latency and a lone
-    wave's issue interval."""
-    iters = {0: 4096, 1: 4096, 2: 4096, 3: 2048, 4: 4096, 5: 8192, 6: 1 << 14, 7: 1 << 14, 8: 1 << 14}
+    instruction classes, LDS bandwidth, dependent LDS read latency, a lone
+    wave's issue interval, and the quad sweep step alone with and without its
+    threshold reads."""
+    iters = {0: 4096, 1: 4096, 2: 4096, 3: 2048, 4: 4096, 5: 8192, 6: 1 << 14, 7: 1 << 14, 8: 1 << 14,
+             9: 20000, 10: 20000, 11: 20000}
     out = {}
     for k, name in mc.PROBES.items():
         fig, sec, work, cyc = mc.probe(k, iters[k])
@@ -702,6 +704,9 @@ def bench_peaks(a, torch, mc):
         "mul_hi_rate_vs_xor": out["valu_mul_hi"]["value"] / out["valu_xor"]["value"],
         "mad_u64_rate_vs_xor": out["valu_mad_u64"]["value"] / out["valu_xor"]["value"],
         "lds_bytes_per_clk_per_cu": out["lds_read_bandwidth"]["value"] / (256 * CLOCK_HZ),
+        "quad_step_cycles_per_attempt": out["quad_step_cycles"]["value"] / 4.0,
+        "quad_step_share_of_threshold_reads": 1.0 - out["quad_step_cycles_no_threshold_reads"]["value"]
+                                              / out["quad_step_cycles"]["value"],
         "shader_clock_hz_seen_by_lone_wave_probe": out["lone_wave_independent_issue_cycles"]["cycles"]
                                                    / out["lone_wave_independent_issue_cycles"]["seconds"]}
     return res

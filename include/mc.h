@@ -433,10 +433,17 @@ mc_status mc_check_levels(mc_ctx *ctx, int32_t size_idx, int64_t *n_bad);
      6     latency of one wave's dependent LDS reads, shader-clock cycles per
            read (including the one instruction that forms the next address);
      7, 8  issue interval of a lone wave, cycles per instruction, for
-           dependent (7) and independent (8) simple VALU instructions.
-   iters (1..2^24) scales the work.  out_host[4]: the figure, the seconds of
-   the timed launch (hipEvents), the work counted (lane-instructions, bytes,
-   reads or instructions), the shader-clock cycles counted (kinds 6..8).
+           dependent (7) and independent (8) simple VALU instructions;
+     9..11 cycles per four-site step of the quad sweep step alone (one wave,
+           16 chains of L = 32, hashed spins, thresholds and random words; no
+           producer waves, barriers or global memory): 9 as the sweeps run
+           it, 10 with its six threshold reads taken from the small pair
+           table at addresses that do not depend on the level, 11 with the
+           thresholds made by arithmetic from the level instead of read.
+   iters (1..2^24) scales the work (rows of 32 sites for kinds 9..11).
+   out_host[4]: the figure, the seconds of the timed launch (hipEvents), the
+   work counted (lane-instructions, bytes, reads, instructions or steps), the
+   shader-clock cycles counted (kinds 6..11).
    Allocates and frees its own device buffers; synchronises hip_stream.
    Errors: MC_EINVAL, MC_ENODEV, MC_ENOMEM, MC_EHIP. */
 mc_status mc_probe(int32_t kind, int32_t iters, void *hip_stream, double *out_host);

@@ -426,7 +426,8 @@ class Graph:
 
 PROBES = {0: "valu_xor", 1: "valu_mul_lo", 2: "valu_mul_hi", 3: "valu_mad_u64", 4: "valu_bitop3",
           5: "lds_read_bandwidth", 6: "lds_dependent_read_cycles", 7: "lone_wave_dependent_issue_cycles",
-          8: "lone_wave_independent_issue_cycles"}
+          8: "lone_wave_independent_issue_cycles", 9: "quad_step_cycles", 10: "quad_step_cycles_pair_table_reads",
+          11: "quad_step_cycles_no_threshold_reads"}
 
 
 def probe(kind, iters, stream=None):

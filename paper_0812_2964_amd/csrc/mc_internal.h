@@ -127,6 +127,9 @@ hipError_t launch_update64(const SizeDev &s, hipStream_t st);
 hipError_t launch_thermo(const SizeDev &s, const double *beta_dev, int n_beta, double *out_dev, hipStream_t st);
 // Count, into s.n_bad, the chains whose level is not half their broken bonds.
 hipError_t launch_check_levels(const SizeDev &s, hipStream_t st);
+// Step-timing probe of the quad step (mc_probe kinds 9-11): mode 0 the sweeps'
+// step, 1 its threshold reads moved to the pair table, 2 no threshold reads.
+hipError_t launch_quad_step_probe(int mode, int rows, int64_t *cyc, uint32_t *out, hipStream_t st);
 
 // Most inverse temperatures one mc_thermo call takes.
 constexpr int kThermoMaxBetas = 1 << 20;

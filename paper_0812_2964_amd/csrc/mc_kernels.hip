@@ -647,8 +647,13 @@ __device__ __forceinline__ uint32_t quad_bcast(uint32_t v) {
 // pair p accepted; jq: the lane's place in its quad; hf0 / hf1: its result
 // flags (jq, its assumed outcome of pair p, in bits 28-29, plus bit 30 when
 // pair p+1's first site is accepted), so that the word selected for the quad
-// carries the step's four flips in bits 28-31.
-template <int L>
+// carries the step's four flips in bits 28-31.  TREAD selects where the six
+// thresholds come from: 0, the level table (the sweeps); 1 and 2 exist for
+// the step-timing probe only (k_quad_step_probe): 1 reads six words of the
+// pair table instead, at addresses formed from the entries alone, and folds
+// the state in afterwards; 2 reads nothing and makes the thresholds from the
+// state with arithmetic.
+template <int L, int TREAD = 0>
 __device__ __forceinline__ void pcq_row(Row<L> &cur, const Row<L> &up, const Row<L> &dn, uint32_t &mib,
                                         uint32_t pair_addr, const uint4 *urow, int cpb, uint32_t selh, uint32_t hym,
                                         uint32_t jq, uint32_t hf0, uint32_t hf1) {
@@ -717,12 +722,29 @@ __device__ __forceinline__ void pcq_row(Row<L> &cur, const Row<L> &up, const Row
         // byte 1 of V (only x) or 0, picked by the lane's selector
         const uint32_t mh = mib + __builtin_amdgcn_perm(ea.x, V, selh);
         const uint32_t Vq = (eb.z & hym) | (eb.y & ~hym);
-        const uint32_t tx = lds_load(mib + sbyte(V, 0));
-        const uint32_t t0 = lds_load(mib + sbyte(ea.x, 0));
-        const uint32_t t1 = lds_load(mib + sbyte(V, 2));
-        const uint32_t qx = lds_load(mh + sbyte(Vq, 0));
-        const uint32_t q0 = lds_load(mh + sbyte(eb.x, 0));
-        const uint32_t q1 = lds_load(mh + sbyte(Vq, 2));
+        uint32_t tx, t0, t1, qx, q0, q1;
+        if constexpr (TREAD == 0) {
+            tx = lds_load(mib + sbyte(V, 0));
+            t0 = lds_load(mib + sbyte(ea.x, 0));
+            t1 = lds_load(mib + sbyte(V, 2));
+            qx = lds_load(mh + sbyte(Vq, 0));
+            q0 = lds_load(mh + sbyte(eb.x, 0));
+            q1 = lds_load(mh + sbyte(Vq, 2));
+        } else if constexpr (TREAD == 1) {
+            tx = lds_load(pair_addr + 64 + sbyte(V, 0)) ^ mib;
+            t0 = lds_load(pair_addr + 128 + sbyte(ea.x, 0)) ^ mib;
+            t1 = lds_load(pair_addr + 192 + sbyte(V, 2)) ^ mib;
+            qx = lds_load(pair_addr + 256 + sbyte(Vq, 0)) ^ mh;
+            q0 = lds_load(pair_addr + 320 + sbyte(eb.x, 0)) ^ mh;
+            q1 = lds_load(pair_addr + 384 + sbyte(Vq, 2)) ^ mh;
+        } else {
+            tx = mib * 0x9E3779B9u;
+            t0 = tx ^ 0x55555555u;
+            t1 = tx ^ 0x33333333u;
+            qx = mh * 0x9E3779B9u;
+            q0 = qx ^ 0x55555555u;
+            q1 = qx ^ 0x33333333u;
+        }
         const bool bx = u4.z <= qx;
         const uint32_t qn = bx ? q1 : q0;
         const uint32_t nA = mh + (uint32_t)(bx ? sbyte(Vq, 3) : sbyte(eb.x, 3));
@@ -848,6 +870,88 @@ template <int L>
 __global__ __launch_bounds__(kPcThreads) void k_sweep_pcq(PcParams p) {
     extern __shared__ __align__(16) uint32_t smem[];
     sweep_tile_pcq<L>(p.s, blockIdx.x * p.cpb, p.cpb, p.R, p.M, p.trace, p.hist, smem);
+}
+
+// ---------------------------------------------------------------------------
+// Timing probe of the quad step (mc_probe kinds 9-11; a measurement, not a
+// step of the method): one wave holding 16 chains of L = 32 with hashed spins,
+// a level table of hashed thresholds (a flip that keeps the level is always
+// accepted) and hashed random words, times `rows` rows of pcq_row with the
+// shader clock, with nothing else on the compute unit: no producer waves, no
+// barriers, no global memory.  The levels are those of the lattices, tracked
+// exactly, so every table read stays inside the table.  out[c] receives chain
+// c's final level, *cyc the cycles of the timed rows.
+// ---------------------------------------------------------------------------
+constexpr int kProbeL = 32, kProbeChains = 16, kProbeR = 8;
+
+__host__ __device__ inline PcLayout quad_probe_layout() {
+    return pc_layout(kProbeL, 1, kProbeL * kProbeL, kProbeL * kProbeL / 2 + 1, kProbeChains, kProbeR);
+}
+
+__device__ __forceinline__ uint32_t probe_hash(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7FEB352Du;
+    x ^= x >> 15;
+    x *= 0x846CA68Bu;
+    x ^= x >> 16;
+    return x;
+}
+
+template <int TREAD>
+__global__ __launch_bounds__(64) void k_quad_step_probe(int rows, int64_t *cyc, uint32_t *out) {
+    constexpr int L = kProbeL, N = L * L, cpb = kProbeChains, R = kProbeR;
+    extern __shared__ __align__(16) uint32_t smem[];
+    const PcLayout lay = quad_probe_layout();
+    char *lds = (char *)smem;
+    uint32_t *slat = (uint32_t *)(lds + lay.lat);
+    uint32_t *stab = (uint32_t *)(lds + lay.tab);
+    uint4 *ptbl = (uint4 *)(lds + lay.pair);
+    uint4 *ubuf = (uint4 *)(lds + lay.ubuf);
+    const int lane = (int)threadIdx.x, cl = lane >> 2, j = lane & 3;
+    for (int i = lane; i < (N + 1) * 5; i += 64) stab[i] = i % 5 == 2 ? 0xFFFFFFFFu : probe_hash(77u * i + 1u);
+    build_pair_table_q(ptbl, lane, 64);
+    for (int i = lane; i < R * (L / 4) * cpb * 4; i += 64) ((uint32_t *)ubuf)[i] = probe_hash((uint32_t)i + 12345u);
+    for (int i = lane; i < L * cpb; i += 64) slat[i] = probe_hash(0x51EDu + (uint32_t)i);
+    __syncthreads();
+    // level = half the broken bonds (right and down neighbours, periodic)
+    uint32_t broken = 0;
+    for (int y = 0; y < L; ++y) {
+        const uint32_t r = slat[y * cpb + cl], d = slat[((y + 1) % L) * cpb + cl];
+        broken += __popc(r ^ ((r >> 1) | (r << 31))) + __popc(r ^ d);
+    }
+    const uint32_t selh = quad_move_selector((uint32_t)j), hym = 0u - (uint32_t)((j >> 1) & 1);
+    const uint32_t hf0 = (uint32_t)j << 28, hf1 = hf0 | (1u << 30);
+    const uint32_t tab_addr = (uint32_t)(size_t)(lds_u32 *)(stab);
+    const uint32_t pair_addr = (uint32_t)(size_t)(lds_u32 *)(ptbl);
+    uint32_t mib = tab_addr + (uint32_t)kLevelBytes * (broken / 2) + 16u;
+    Row<L> up, cur, dn;
+    up.w[0] = slat[(L - 1) * cpb + cl];
+    cur.w[0] = slat[cl];
+    dn.w[0] = slat[cpb + cl];
+    const long long t0 = clock64();
+    for (int r = 0; r < rows; ++r) {
+        const int y = r % L;
+        pcq_row<L, TREAD>(cur, up, dn, mib, pair_addr, ubuf + (size_t)(r % R) * (L / 4) * cpb + cl, cpb, selh, hym,
+                          (uint32_t)j, hf0, hf1);
+        slat[y * cpb + cl] = cur.w[0];  // the four lanes of the quad hold the same row
+        up = cur;
+        cur = dn;
+        dn.w[0] = slat[((y + 2) % L) * cpb + cl];
+    }
+    const long long t1 = clock64();
+    if (lane == 0) *cyc = t1 - t0;
+    if (j == 0) out[cl] = (mib - tab_addr - 16u) / (uint32_t)kLevelBytes;
+}
+
+hipError_t launch_quad_step_probe(int mode, int rows, int64_t *cyc, uint32_t *out, hipStream_t st) {
+    const size_t bytes = quad_probe_layout().total;
+    if (mode == 0)
+        hipLaunchKernelGGL(k_quad_step_probe<0>, dim3(1), dim3(64), bytes, st, rows, cyc, out);
+    else if (mode == 1)
+        hipLaunchKernelGGL(k_quad_step_probe<1>, dim3(1), dim3(64), bytes, st, rows, cyc, out);
+    else
+        hipLaunchKernelGGL(k_quad_step_probe<2>, dim3(1), dim3(64), bytes, st, rows, cyc, out);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -1246,7 +1350,7 @@ __device__ void build_pair_parity_q(uint4 *tbl, int tid, int nthreads) {
 template <int L, bool TAB_LDS>
 __device__ __forceinline__ void bigq_row_p(uint32_t *lat, size_t P, int c, int y, uint32_t &S,
                                            const uint32_t *tabc, uint32_t pair_addr, const uint4 *urow, int cpb,
-                                           uint32_t hym, uint32_t sel_h, uint32_t f0, uint32_t f1) {
+                                           uint32_t hym, uint32_t sel_h, uint32_t f0, uint32_t f1, uint32_t jq) {
     static_assert(L % 4 == 0 && L > 64, "steps of four sites; at least three words per row");
     constexpr int W = (L + 31) / 32;
     constexpr int NB = L - 32 * (W - 1);
@@ -1273,9 +1377,22 @@ __device__ __forceinline__ void bigq_row_p(uint32_t *lat, size_t P, int c, int y
         const uint32_t hs = (hb << 1) | carry;
         carry = (hb >> 31) & 1u;
         const uint4 *uw4 = urow + (size_t)w * 8 * cpb;
+        // the entry addresses of the word's 16 pairs, shared out over the
+        // quad as in the L <= 64 kernel: lane jq forms those of pairs 4k + jq,
+        // and a step takes the two it needs from their lanes with a DPP
+        // broadcast (pairs past the word's last site are formed, never read)
+        uint32_t own[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t bq = (uint32_t)(8 * k) + 2u * jq;
+            const uint32_t idx = __builtin_amdgcn_ubfe(P0, bq, 2) | (__builtin_amdgcn_ubfe(P1, bq, 2) << 2) |
+                                 (__builtin_amdgcn_ubfe(hs, bq, 2) << 4);
+            own[k] = pair_addr + idx * 32u;
+        }
         auto entry = [&](int p, uint4 &h0, uint4 &h1) {
-            const uint32_t idx = ((P0 >> (2 * p)) & 3u) | (((P1 >> (2 * p)) & 3u) << 2) | (((hs >> (2 * p)) & 3u) << 4);
-            const uint32_t a = pair_addr + idx * 32u;
+            const uint32_t v = own[p >> 2];
+            const uint32_t a = (p & 3) == 0 ? quad_bcast<0x00>(v) : (p & 3) == 1 ? quad_bcast<0x55>(v)
+                             : (p & 3) == 2 ? quad_bcast<0xAA>(v) : quad_bcast<0xFF>(v);
             h0 = lds_load96(a);
             h1 = lds_load96(a + 16u);
         };
@@ -1404,7 +1521,7 @@ __device__ __forceinline__ void sweep_tile_bigq(const SizeDev &s, int c0, int cp
                 const uint4 *urow = ub + (size_t)rr * (L / 4) * cpb + cl;
                 if (par)
                     bigq_row_p<L, TAB_LDS>(s.lat, (size_t)s.P, c, y0 + rr, S, s.tabc, pair_addr, urow, cpb, hym,
-                                           sel_h, f0, f1);
+                                           sel_h, f0, f1, (uint32_t)j);
                 else
                     bigq_row<L, TAB_LDS>(s.lat, (size_t)s.P, c, y0 + rr, m, bs, B0, sB, s.tabc, pair_addr, urow,
                                          cpb, hym, sel_h, f0, f1);

@@ -3,7 +3,9 @@
 // instruction classes of a Metropolis attempt (simple, 32-bit multiplies,
 // 64-bit multiply-add, three-input bit operations), LDS bandwidth and the
 // latency of dependent LDS reads, and the issue interval of a lone wave for
-// dependent and for independent instructions.  The measured figures replace
+// dependent and for independent instructions, and the cycles of the quad
+// sweep step alone (with its threshold reads, with them moved, without them).
+// The measured figures replace
 // assumed peaks in the roofline of the sweep kernels: a Markov chain's
 // attempts are strictly serial, so what one wave can issue bounds a chain.
 #include <hip/hip_runtime.h>
@@ -17,6 +19,7 @@ namespace mcgpu {
 namespace {
 
 constexpr int kUnroll = 16;   // asm groups per loop iteration
+constexpr int kQuadProbeL = 32;  // lattice of the quad-step probe (k_quad_step_probe)
 constexpr int kChains = 8;    // independent registers per thread
 
 // One group of kChains independent instructions of a class, on registers
@@ -148,8 +151,8 @@ __global__ __launch_bounds__(64) void k_issue(uint32_t *out, int64_t *cycles, in
 using namespace mcgpu;
 
 extern "C" mc_status mc_probe(int32_t kind, int32_t iters, void *hip_stream, double *out_host) {
-    if (!out_host || kind < 0 || kind > 8 || iters < 1 || iters > (1 << 24)) {
-        set_last_error("mc_probe: kind must be 0..8, iters 1..2^24, out_host non-null");
+    if (!out_host || kind < 0 || kind > 11 || iters < 1 || iters > (1 << 24)) {
+        set_last_error("mc_probe: kind must be 0..11, iters 1..2^24, out_host non-null");
         return MC_EINVAL;
     }
     int dev = 0, n_cu = 0;
@@ -186,7 +189,10 @@ extern "C" mc_status mc_probe(int32_t kind, int32_t iters, void *hip_stream, dou
         case 5: hipLaunchKernelGGL(k_lds_bw, dim3(lds_blocks), dim3(256), 0, st, out, iters); break;
         case 6: hipLaunchKernelGGL(k_lds_latency, dim3(1), dim3(64), 0, st, out, cyc, iters); break;
         case 7: hipLaunchKernelGGL(k_issue<true>, dim3(1), dim3(64), 0, st, out, cyc, iters, b); break;
-        default: hipLaunchKernelGGL(k_issue<false>, dim3(1), dim3(64), 0, st, out, cyc, iters, b); break;
+        case 8: hipLaunchKernelGGL(k_issue<false>, dim3(1), dim3(64), 0, st, out, cyc, iters, b); break;
+        default:
+            if (launch_quad_step_probe(kind - 9, iters, cyc, out, st) != hipSuccess) status = MC_EHIP;
+            break;
         }
         (void)hipEventRecord(e1, st);
         if (hipEventSynchronize(e1) != hipSuccess || hipGetLastError() != hipSuccess) status = MC_EHIP;
@@ -204,8 +210,10 @@ extern "C" mc_status mc_probe(int32_t kind, int32_t iters, void *hip_stream, dou
             work = per_thread * valu_blocks * 64;       // lane-instructions
         else if (kind == 5)
             work = per_thread * lds_blocks * 256 * 16;  // bytes
-        else
+        else if (kind <= 8)
             work = (double)iters * kUnroll * (kind == 6 ? 1 : kChains);  // dependent reads / instructions of the wave
+        else
+            work = (double)iters * (kQuadProbeL / 4);  // four-site steps of one chain
         out_host[0] = chip ? work / s : (double)cycles / work;  // rate per second, or cycles per item
         out_host[1] = s;
         out_host[2] = work;

@@ -117,6 +117,36 @@ def test_graph_replays_equal_eager_iterations():
     eager.close()
 
 
+def test_twenty_iteration_graph_of_the_batched_workload():
+    """The batched workload's five sizes at their full chain counts (2048
+    each), the recursion's first 20 iterations captured in ONE graph (at 20
+    sweeps per iteration instead of 10^5), equal 20 eager iterations bit for
+    bit: weights, counters, progress, the last iteration's traces and cuts."""
+    mc = _mc()
+    Ls, P, M, n_it = [16, 24, 32, 48, 64], 2048, 20, 20
+    sizes = [(L, P, 1, 1) for L in Ls]
+    g_ctx = mc.Context(sizes)
+    e_ctx = mc.Context(sizes)
+    n = len(Ls)
+    trs = [g_ctx.new_trace(M, i) for i in range(n)]
+    hs = [g_ctx.new_hist(i) for i in range(n)]
+    cuts = [g_ctx.new_cut(i) for i in range(n)]
+    g = g_ctx.graph(M, n_it, trs, hs, cuts)
+    g.launch()
+    g_ctx.sync()
+    ref = _iterate(e_ctx, M, n_it)
+    for i in range(n):
+        tr_last, cut_last, _, w_last = ref[i][-1]
+        assert np.array_equal(_np(trs[i]).astype(np.int32), tr_last), Ls[i]
+        assert np.array_equal(_np(cuts[i]), cut_last), Ls[i]
+        assert np.array_equal(g_ctx.weights(i).view(np.uint64), w_last.view(np.uint64)), Ls[i]
+        assert g_ctx.progress(i) == e_ctx.progress(i) and g_ctx.progress(i)[0] == n_it
+        assert g_ctx.counters(i) == e_ctx.counters(i)
+    g.close()
+    g_ctx.close()
+    e_ctx.close()
+
+
 def test_launch_configuration_never_changes_results():
     mc = _mc()
     M = 15
