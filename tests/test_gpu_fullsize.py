@@ -133,3 +133,85 @@ def test_learned_prediction_and_initialisation_at_L256():
         _, _, otr, _ = O.sweeps(L, 1, bs, c, s0, m0, 0, M, pw)
         assert np.array_equal(trace[c], otr), c
     ctx.close()
+
+
+def test_batched_workload_two_iterations_as_benchmarked(capsys):
+    """The batched workload exactly as the benchmark times it: L = 16, 24,
+    32, 48, 64 with 2048 chains each, autotuned, one HIP graph of a whole
+    iteration (10^5 sweeps of every chain in one persistent launch, the
+    joints and the updates) replayed twice from ln w = 0.  For every size the
+    oracle redoes both joints over all 2048 traces (cut points exactly) and
+    both updates (ln w bit for bit, which pins each joined histogram, since
+    ln is one-to-one on the counts), and replays sampled chains over both
+    iterations, the second under the first update's weight."""
+    import paper_0812_2964_amd as mc
+    from concurrent.futures import ThreadPoolExecutor
+
+    Ls, P, M, bs = [16, 24, 32, 48, 64], 2048, 100000, 1
+    sample = (0, 1001, 2047)
+    t0 = time.perf_counter()
+
+    def say(msg):
+        with capsys.disabled():
+            print("  batched, two iterations: %s (%.0f s)" % (msg, time.perf_counter() - t0), flush=True)
+
+    ctx = mc.Context([(L, P, 1, bs) for L in Ls])
+    ctx.autotune(200)
+    assert all(ctx.launch(i)[2] for i in range(len(Ls)))  # one batched launch
+    trs = [ctx.new_trace(M, i) for i in range(len(Ls))]
+    hs = [ctx.new_hist(i) for i in range(len(Ls))]
+    cuts = [ctx.new_cut(i) for i in range(len(Ls))]
+    g = ctx.graph(M, 1, trs, hs, cuts)
+    got = []  # per iteration: per size (trace int16, cuts, ln w, flat, seam)
+    pool = ThreadPoolExecutor(max_workers=8)
+
+    def replay(L, c, s, m, g0, w):
+        return O.sweeps(L, 1, bs, c, s, m, g0, M, w)
+
+    # iteration 1 from ln w = 0: the oracle's replays run while the GPU sweeps
+    first = {}
+    for L in Ls:
+        N = L * L
+        for c in sample:
+            s0 = O.init_chain(L, 1, c)
+            first[(L, c)] = pool.submit(replay, L, c, s0, (O.energy(L, s0) + 2 * N) // 4, 0,
+                                        np.zeros((N >> bs) + 1))
+    for it in range(2):
+        g.launch()
+        ctx.sync()
+        got.append([(trs[i].cpu().numpy(), cuts[i].cpu().numpy(), ctx.weights(i), ctx.progress(i)[2],
+                     ctx.counters(i)[0]) for i in range(len(Ls))])
+        say("iteration %d on the GPU done" % (it + 1))
+    levels = [ctx.levels(i) for i in range(len(Ls))]
+    spins = [{c: ctx.spins(c, i) for c in sample} for i in range(len(Ls))]
+    g.close()
+    ctx.close()
+    second = {}
+    for i, L in enumerate(Ls):
+        N = L * L
+        w, seam = np.zeros((N >> bs) + 1), -1
+        for it in range(2):
+            tr, gcut, gw, gflat, gseam = got[it][i]
+            tr32 = tr.astype(np.int32)
+            ocut, oH, oret, osig = O.join(L, bs, 1, tr32, w, seam, it)
+            assert np.array_equal(gcut, ocut), (L, it)
+            assert gseam == osig, (L, it)
+            ow, oflat = O.update(L, bs, oH, w)
+            assert gflat == oflat, (L, it)
+            assert np.array_equal(gw.view(np.uint64), ow.view(np.uint64)), (L, it)
+            if it == 0:
+                for c in sample:
+                    s, m, otr, _ = first[(L, c)].result()
+                    assert np.array_equal(tr32[c], otr), (L, c, it)
+                    second[(L, c)] = pool.submit(replay, L, c, s, m, M, ow)
+            w, seam = ow, osig
+            del tr32
+        say("oracle joints and updates of L = %d done" % L)
+    for i, L in enumerate(Ls):
+        tr32 = got[1][i][0].astype(np.int32)
+        for c in sample:
+            s, m, otr, _ = second[(L, c)].result()
+            assert np.array_equal(tr32[c], otr), (L, c, 1)
+            assert np.array_equal(spins[i][c], s) and levels[i][c] == m, (L, c)
+    pool.shutdown()
+    say("oracle replays done")
