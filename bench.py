@@ -437,7 +437,8 @@ def bench_batched(a, torch, mc):
     res["iterations_to_flat"] = flats
     if not a.no_cpu:
         log("bench batched: timing the CPU oracle on a sample")
-        res["cpu_baseline"] = cpu_baseline_batched(Ls, weights, 4, a.cpu_sweeps // 2)
+        # about 10 s of host work per leg on a current server core
+        res["cpu_baseline"] = cpu_baseline_batched(Ls, weights, 4, 4 * a.cpu_sweeps)
     return res
 
 
