@@ -100,6 +100,9 @@ def parse():
     ap.add_argument("--state-in", default=None, help="large: resume from this checkpoint")
     ap.add_argument("--state-out", default=None, help="large: checkpoint to this file after every iteration")
     ap.add_argument("--parts", type=int, default=4, help="large: launches per round (progress between them)")
+    ap.add_argument("--stage128", type=int, default=0, help="learned256: also run L = 128 from the network's "
+                    "proposal for at most this many iterations, and train on it if it flattens")
+    ap.add_argument("--no-arms", action="store_true", help="learned256: stop after the training stages")
     ap.add_argument("--budget-s", type=float, default=None, help="large: start no iteration that would end after "
                                                                   "this many seconds since the start")
     return ap.parse_args()
@@ -617,6 +620,33 @@ def bench_learned256(a, torch, mc):
     loss = ini.fit(steps=4000, lr=2e-3)
     log("bench learned256: L = 64 flat at %s; trained on %s (loss %.3g, %.0f s)"
         % (flat, [k for k, v in stages.items() if v["first_flat"]], loss, time.perf_counter() - t0))
+    if a.stage128:
+        t2 = time.perf_counter()
+
+        def progress(done):
+            if done % 20 == 0:
+                log("bench learned256: L = 128 from the network, %d iterations (%.0f s)"
+                    % (done, time.perf_counter() - t2))
+
+        w128, flat, done = run_to_flat(128, P, M, a.stage128, lnW0=ini.predict(128), extra=4, progress=progress)
+        stages[128] = {"from": "network (8, 16, 32, 64)", "first_flat": flat, "iterations": done,
+                       "seconds": time.perf_counter() - t2}
+        if flat is not None:
+            ini.add(128, w128)
+            loss = ini.fit(steps=4000, lr=2e-3)
+        log("bench learned256: L = 128 flat at %s after %d iterations; trained on %s (loss %.3g, %.0f s)"
+            % (flat, done, [k for k, v in stages.items() if v["first_flat"]], loss, time.perf_counter() - t0))
+    if a.no_arms:
+        st128 = stages.get(128)
+        att = (st128["iterations"] * P * M * 128 * 128) if st128 else 0
+        res = base_record(a, att / st128["seconds"] if st128 else 0.0,
+                          st128["seconds"] / max(1, st128["iterations"]) * 1e3 if st128 else 0.0,
+                          {"workload": "training stages of the learned initial weight, 4096 chains x %d sweeps per "
+                                       "iteration: L = 8, 16, 32 from ln w = 0, 64 and 128 from the network's "
+                                       "proposal" % M, "chains": P, "sweeps_per_iter": M})
+        res["training"] = {"stages": {str(k): v for k, v in stages.items()}, "loss": loss}
+        res["iterations_to_flat"] = {str(k): v["first_flat"] for k, v in stages.items()}
+        return res
     metrics = Metrics(a.metrics)
     arms = {}
     finals = {}
@@ -670,7 +700,8 @@ def bench_learned256(a, torch, mc):
     res = base_record(a, att / sec, sec / max(1, sum(v["iterations_run"] for v in arms.values())) * 1e3,
                       {"workload": "learned initial weight for L=256, 4096 chains x %d sweeps per iteration, width-8 "
                                    "bins, seed 1, cap %d iterations per arm; network trained on converged ln w of "
-                                   "L=8, 16, 32, 64" % (M, cap), "L": Lt, "chains": P, "sweeps_per_iter": M,
+                                   "L=%s" % (M, cap, ", ".join(str(k) for k, v in stages.items() if v["first_flat"])),
+                       "L": Lt, "chains": P, "sweeps_per_iter": M,
                        "cap": cap})
     res["training"] = {"stages": {str(k): v for k, v in stages.items()}, "loss": loss}
     res["arms"] = arms
