@@ -103,6 +103,8 @@ def parse():
     ap.add_argument("--stage128", type=int, default=0, help="learned256: also run L = 128 from the network's "
                     "proposal for at most this many iterations, and train on it if it flattens")
     ap.add_argument("--no-arms", action="store_true", help="learned256: stop after the training stages")
+    ap.add_argument("--graph-iters", type=int, default=1, help="batched: iterations captured in each timed graph "
+                    "(--steps a multiple of it; the warmup then runs as one graph of --warmup iterations)")
     ap.add_argument("--budget-s", type=float, default=None, help="large: start no iteration that would end after "
                                                                   "this many seconds since the start")
     return ap.parse_args()
@@ -387,13 +389,32 @@ def bench_batched(a, torch, mc):
     trs = [ctx.new_trace(M, i) for i in range(len(Ls))]
     hs = [ctx.new_hist(i) for i in range(len(Ls))]
     cuts = [ctx.new_cut(i) for i in range(len(Ls))]
-    g = ctx.graph(M, 1, trs, hs, cuts)
+    # launch units: (graph, iterations it holds, timed); with --graph-iters G > 1
+    # the warmup is one graph of W iterations and the timed steps are graphs of
+    # G iterations each (one launch per G steps), else one graph of one
+    # iteration is replayed once per step
+    gi = max(1, a.graph_iters)
+    if a.steps % gi:
+        raise SystemExit("--steps must be a multiple of --graph-iters")
+    graphs = []
+    if gi == 1:
+        g1 = ctx.graph(M, 1, trs, hs, cuts)
+        graphs.append(g1)
+        units = [(g1, 1, s >= a.warmup) for s in range(a.warmup + a.steps)]
+    else:
+        units = []
+        if a.warmup:
+            graphs.append(ctx.graph(M, a.warmup, trs, hs, cuts))
+            units.append((graphs[-1], a.warmup, False))
+        graphs.append(ctx.graph(M, gi, trs, hs, cuts))
+        units += [(graphs[-1], gi, True)] * (a.steps // gi)
     metrics = Metrics(a.metrics)
     ev = []
     elapsed = 0.0
-    for s in range(a.warmup + a.steps):
-        timed = s >= a.warmup
-        if s == a.warmup:
+    done = 0
+    t0 = None
+    for g, n_it, timed in units:
+        if timed and t0 is None:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -402,13 +423,15 @@ def bench_batched(a, torch, mc):
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
+        done += n_it
         if timed:
-            ev.append(ms)
+            ev += [ms / n_it] * n_it
             elapsed = time.perf_counter() - t0
         for i, L in enumerate(Ls):
-            metrics.write(iteration_record(ctx, i, L, P, M, s + 1, ms))
-        log("bench batched: %s step %d done (%.0f ms%s)" % ("timed" if timed else "warmup", s + 1, ms,
-                                                          ", %.1f s so far" % elapsed if timed else ""))
+            metrics.write(iteration_record(ctx, i, L, P, M, done, ms / n_it))
+        log("bench batched: %s step%s %d done (%.0f ms per step%s)"
+            % ("timed" if timed else "warmup", "s up to" if n_it > 1 else "", done, ms / n_it,
+               ", %.1f s so far" % elapsed if timed else ""))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     metrics.close()
@@ -416,21 +439,24 @@ def bench_batched(a, torch, mc):
     iters_run = ctx.progress(0)[0]
     weights = [ctx.weights(i) for i in range(len(Ls))]
     att = P * M * sum(L * L for L in Ls)
-    g.close()
+    for g in graphs:
+        g.close()
     ctx.close()
     launch_s = sum(ev) / len(ev) / 1e3
     res = base_record(a, a.steps * att / elapsed, elapsed / a.steps * 1e3,
                       {"workload": "batched uneven L in {16,24,32,48,64}, %d chains each x %d sweeps per iteration "
                                    "in one persistent launch, width-8 energy bins, recursion from ln w = 0, seed 1; "
                                    "one step = one HIP-graph-captured iteration (sweeps + joints + weight updates of "
-                                   "every size)" % (P, M),
+                                   "every size)%s" % (P, M, "; the timed steps captured %d iterations to a graph"
+                                                       % gi if gi > 1 else ""),
                        "L": Ls, "chains_per_L": P, "sweeps_per_iter": M, "parallelism": "chains",
                        "chains_per_block": cpbs, "kernel_kinds": [p_[1] for p_ in plans]})
     res["roofline"] = roofline(att, launch_s, traffic_from_profiles("k_sweep_batched_5L_2048x1e5_counters.md",
                                                                     BATCHED_WORKLOAD))
     res["roofline"]["kernel"] = "k_sweep_batched (mc_run_chains, one persistent launch of the five sizes)"
-    res["roofline"]["kernel_ms_basis"] = ("HIP events around each graph replay on the context's stream: the sweep "
-                                          "launch plus the joints and updates of the five sizes (a few ms)")
+    res["roofline"]["kernel_ms_basis"] = ("HIP events around each graph replay on the context's stream%s: the sweep "
+                                          "launch plus the joints and updates of the five sizes (a few ms)"
+                                          % (", divided by the %d iterations it holds" % gi if gi > 1 else ""))
     cc = chain_ceiling(mc, plans[Ls.index(max(Ls))][1], att, M * max(Ls) ** 2)
     if cc is not None:
         cc["frac"] = (att / launch_s) / cc["attempts_per_s"]
