@@ -1085,6 +1085,10 @@ def main():
         print("bench.py runs on one GPU only: the chains of one ensemble live on a single device here "
               "(sharding across GPUs is a design note, not built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if a.workload == "batched" and (a.graph_iters < 1 or a.steps % a.graph_iters):
+        print("bench.py: --steps (%d) must be a multiple of --graph-iters (%d >= 1)" % (a.steps, a.graph_iters),
+              file=sys.stderr)
+        sys.exit(2)
     import torch
 
     import paper_0812_2964_amd as mc

@@ -49,6 +49,12 @@ def test_more_than_one_gpu_is_refused():
     assert p.returncode != 0 and "one GPU" in (p.stdout + p.stderr)
 
 
+def test_graph_iterations_must_divide_the_steps():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--graph-iters", "3", "--steps", "4"],
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode == 2 and "multiple of --graph-iters" in p.stderr
+
+
 def test_traffic_only_for_current_source_and_workload(tmp_path, monkeypatch):
     """A counter summary is used only when its kernel source hash and its
     workload line match."""
